@@ -1,0 +1,176 @@
+/*
+ * fo_stokes.h -- C ABI of the MI355X (gfx950) first-order Stokes assembly library.
+ *
+ * The library evaluates, on one GPU, the finite-element residual F(U) and the
+ * Newton Jacobian J = dF/dU of the first-order (Blatter-Pattyn) Stokes
+ * equations for ice flow (arXiv:2204.04321, Sec. 2, eqs. FOStokes, effvisc,
+ * effeps and the bed sliding condition; discrete form eq. residual of Sec. 3.1)
+ * on meshes extruded from a 2D triangulation (wedges) or quadrilateral mesh
+ * (hexahedra), and solves F(U) = 0 by damped Newton (eq. linearsystem).
+ *
+ * Conventions (all entry points):
+ *   - Ordering.  Base vertex v (a "column") at level k (k = 0 at the bed,
+ *     k = L at the surface) is node v*(L+1)+k; dof 2*node+c, c = 0 for u
+ *     (x-velocity) and c = 1 for v (y-velocity).  Node elevation
+ *     z = (s - H) + sigma_k H.  Units: m, yr, Pa.
+ *   - Jacobian storage.  CSR with one row per dof; a row holds every dof that
+ *     shares a cell with the row's node (structural zeros included), columns
+ *     sorted ascending.  rowptr is int64 [n_dofs + 1], colidx int32 [nnz].
+ *   - Memory.  Pointers named *_dev are device pointers owned by the caller
+ *     (e.g. PyTorch tensors on the current HIP device).  Host arrays in
+ *     fo_mesh_desc are read only during fo_mesh_create.  The opaque fo_mesh
+ *     owns its device tables (connectivity, geometry, pattern) until
+ *     fo_mesh_destroy.
+ *   - Streams.  `stream` is a hipStream_t (NULL = default stream).  Assembly
+ *     calls are asynchronous and stream-ordered; fo_mesh_create and
+ *     fo_newton_solve synchronise the stream before returning.
+ *   - Errors.  Every call returns an fo_status; on failure fo_last_error()
+ *     gives a message (thread-local).  Kernel launch failures give FO_EDEVICE.
+ */
+#ifndef FO_STOKES_H
+#define FO_STOKES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FO_OK = 0,
+  FO_EINVAL = -1,        /* bad argument: null pointer, size, enum value */
+  FO_ENOMEM = -2,        /* device or host allocation failed */
+  FO_EDEVICE = -3,       /* HIP runtime or kernel launch error */
+  FO_EDEGENERATE = -4,   /* mesh invalid: H <= 0, non-positive cell area, bad sigma */
+  FO_ENONFINITE = -5,    /* NaN/Inf met in a residual norm (Newton) */
+  FO_ENOTCONV = -6       /* Newton hit its iteration cap or the line search failed */
+} fo_status;
+
+typedef enum { FO_WEDGE6 = 6, FO_HEX8 = 8 } fo_elem;     /* triangle / quad base cells */
+typedef enum { FO_F64 = 0, FO_F32 = 1 } fo_dtype;         /* Jacobian value type */
+typedef enum { FO_JAC_NEWTON = 0, FO_JAC_PICARD = 1 } fo_jac_kind;
+
+/* Mesh and physical constants (Sec. 2: A, n, rho, g; beta of the sliding law). */
+typedef struct {
+  int32_t elem;              /* FO_WEDGE6 or FO_HEX8 */
+  int32_t n_base_verts;      /* V >= 3 */
+  int32_t n_base_cells;      /* T >= 1 */
+  int32_t n_layers;          /* L >= 1 */
+  const double *base_xy;     /* host [V][2], m */
+  const int32_t *base_cells; /* host [T][3 or 4], counter-clockwise, 0 <= id < V */
+  const double *surface;     /* host [V], s (m) */
+  const double *thickness;   /* host [V], H > 0 (m) */
+  const double *beta;        /* host [V], beta >= 0 (Pa yr / m) */
+  const double *sigma;       /* host [L+1], 0 = sigma_0 < ... < sigma_L = 1; NULL = uniform */
+  double A;                  /* rate factor > 0, Pa^-n yr^-1 */
+  double n;                  /* Glen exponent >= 1 */
+  double rho;                /* ice density > 0, kg m^-3 */
+  double g;                  /* gravity > 0, m s^-2 */
+  double eps0;               /* strain-rate regularisation >= 0, yr^-1 */
+} fo_mesh_desc;
+
+typedef struct fo_mesh fo_mesh;
+
+/* Validate the description, build the column-major numbering, the Jacobian
+ * pattern and per-column tables once (the paper's memoisation of
+ * solution-independent data, Sec. 4.1) and upload them.  On FO_EDEGENERATE
+ * nothing is allocated.  Synchronises `stream`. */
+fo_status fo_mesh_create(const fo_mesh_desc *desc, void *stream, fo_mesh **out);
+void fo_mesh_destroy(fo_mesh *mesh);
+
+/* Sizes: nodes V*(L+1), dofs 2*nodes, cells T*L, Jacobian nonzeros.  Any output may be NULL. */
+fo_status fo_mesh_info(const fo_mesh *mesh, int64_t *n_nodes, int64_t *n_dofs,
+                       int64_t *n_cells, int64_t *nnz);
+
+/* Copy the Jacobian pattern into caller buffers rowptr_dev [n_dofs+1] (int64)
+ * and colidx_dev [nnz] (int32).  Either may be NULL. */
+fo_status fo_jacobian_pattern(const fo_mesh *mesh, int64_t *rowptr_dev, int32_t *colidx_dev,
+                              void *stream);
+
+/* Residual F(U) of eq. (residual): viscous term with the regularised Glen
+ * viscosity 1/2 A^(-1/n) (eps_e^2 + eps0^2)^((1-n)/(2n)) (eqs. effvisc,
+ * effeps), gravity rho g grad s, and bed friction beta u.  U_dev, R_dev: FP64
+ * [n_dofs]; R is overwritten. */
+fo_status fo_assemble_residual(const fo_mesh *mesh, const double *U_dev, double *R_dev,
+                               void *stream);
+
+/* Jacobian J = dF/dU (eq. linearsystem) by forward-mode AD over the element
+ * dofs, values written into Jvals_dev [nnz] of type `dtype` (FO_F64: double,
+ * FO_F32: float; FP32 values come from FP32 derivative lanes over an FP64
+ * primal evaluation).  kind = FO_JAC_PICARD drops the viscosity-derivative
+ * term.  If R_dev is not NULL the FP64 residual is written too, from the same
+ * pass.  Jvals and R are overwritten. */
+fo_status fo_assemble_jacobian(const fo_mesh *mesh, const double *U_dev, double *R_dev,
+                               void *Jvals_dev, int32_t dtype, int32_t kind, void *stream);
+
+/* Shallow-ice velocity profile (plain Newton initial guess, not part of the
+ * paper): U = u_b - 2A/(n+1) (rho g)^n |grad s|^(n-1) grad s [H^(n+1) - (s-z)^(n+1)]
+ * with u_b = -rho g H grad s / beta capped at 1e4 m/yr; grad s at a vertex is
+ * the area-weighted mean of the adjacent base cells' gradients.  U_dev [n_dofs]. */
+fo_status fo_initial_guess_sia(const fo_mesh *mesh, double *U_dev, void *stream);
+
+/* ---- Newton solve (eq. linearsystem: J(U_k) delta = -F(U_k), U_{k+1} = U_k + alpha_k delta) ---- */
+typedef enum { FO_INIT_USER = 0, FO_INIT_SIA = 1 } fo_init;
+
+typedef struct {
+  double tol;              /* stop when ||F(U)||_2 <= tol ||F(0)||_2 (default 1e-8) */
+  int32_t max_newton;      /* Newton iteration cap (50) */
+  double lin_rtol;         /* GMRES relative residual tolerance (1e-6) */
+  int32_t gmres_restart;   /* GMRES restart length, 1..500 (100) */
+  int32_t max_lin;         /* GMRES iterations per Newton step (500) */
+  int32_t jac_dtype;       /* FO_F64 or FO_F32 Jacobian values for GMRES and preconditioner */
+  int32_t max_backtracks;  /* line-search halvings of alpha (10) */
+  int32_t init;            /* FO_INIT_USER: U_dev holds the guess; FO_INIT_SIA: shallow-ice guess */
+} fo_newton_opts;
+
+typedef struct {
+  int32_t status;          /* fo_status of the solve */
+  int32_t newton_its;
+  int64_t lin_its;         /* GMRES iterations summed over Newton steps */
+  int32_t residual_calls;  /* residual-only assemblies (line search, norms) */
+  int32_t jacobian_calls;  /* residual + Jacobian assemblies */
+  int32_t backtracks;
+  double f0_norm;          /* ||F(0)||_2 */
+  double final_norm;       /* ||F(U)||_2 at return */
+  double final_rel;        /* final_norm / f0_norm */
+  double ms_total_fill;    /* timers named as in the paper's Sec. 5 tables */
+  double ms_prec_construction;
+  double ms_linear_solve;
+  double ms_total_solve;
+  double res_hist[64];     /* ||F||/||F(0)|| before each Newton step (first 64) */
+} fo_newton_report;
+
+void fo_newton_default_opts(fo_newton_opts *opts);
+
+/* Device workspace needed by fo_newton_solve for these options (0 on bad options):
+ * Jacobian values, GMRES basis (restart+1 vectors), column factors, vectors. */
+size_t fo_newton_workspace_bytes(const fo_mesh *mesh, const fo_newton_opts *opts);
+
+/* Damped Newton with GMRES(restart) right-preconditioned by block LU of each vertical
+ * column's 2(L+1) x 2(L+1) block (block-tridiagonal, no pivoting) and a backtracking
+ * line search (alpha = 1, 1/2, ... accepting a decrease by (1 - 1e-4 alpha)).  U_dev
+ * [n_dofs] holds the initial guess (unless init = FO_INIT_SIA) and returns the last
+ * accepted iterate.  workspace_dev: caller-owned device memory, 256-byte aligned, at
+ * least fo_newton_workspace_bytes.  Returns FO_OK on convergence, FO_ENOTCONV (cap or
+ * line search), FO_ENONFINITE; the report is filled in every case.  Synchronises. */
+fo_status fo_newton_solve(const fo_mesh *mesh, double *U_dev, const fo_newton_opts *opts,
+                          fo_newton_report *report, void *workspace_dev, size_t workspace_bytes,
+                          void *stream);
+
+/* Measurement support: while enabled, every assembly call records HIP events on
+ * its stream around its main assembly kernel (not the zero fills).
+ * fo_profile_read synchronises on the last event, returns the summed kernel
+ * time in milliseconds and the launch count since the last read, and resets
+ * both.  Enabling allocates a few events; disabling releases them. */
+fo_status fo_profile_enable(fo_mesh *mesh, int32_t on);
+fo_status fo_profile_read(fo_mesh *mesh, double *kernel_ms, int64_t *launches);
+
+const char *fo_status_string(fo_status s);
+const char *fo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FO_STOKES_H */

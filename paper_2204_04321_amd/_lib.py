@@ -1,0 +1,83 @@
+"""ctypes view of libfo_stokes.so (declarations mirror include/fo_stokes.h).
+
+The library must be built in-tree (python -m paper_2204_04321_amd.build); there is
+no fallback: loading fails loudly when the shared object is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfo_stokes.so")
+
+FO_OK, FO_EINVAL, FO_ENOMEM, FO_EDEVICE, FO_EDEGENERATE, FO_ENONFINITE, FO_ENOTCONV = 0, -1, -2, -3, -4, -5, -6
+FO_WEDGE6, FO_HEX8 = 6, 8
+FO_F64, FO_F32 = 0, 1
+FO_JAC_NEWTON, FO_JAC_PICARD = 0, 1
+
+
+class FoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [
+        ("elem", C.c_int32), ("n_base_verts", C.c_int32), ("n_base_cells", C.c_int32),
+        ("n_layers", C.c_int32),
+        ("base_xy", C.c_void_p), ("base_cells", C.c_void_p), ("surface", C.c_void_p),
+        ("thickness", C.c_void_p), ("beta", C.c_void_p), ("sigma", C.c_void_p),
+        ("A", C.c_double), ("n", C.c_double), ("rho", C.c_double), ("g", C.c_double),
+        ("eps0", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def _declare(lib):
+    vp, i32, i64p = C.c_void_p, C.c_int32, C.POINTER(C.c_int64)
+    sig = {
+        "fo_mesh_create": (C.c_int, [C.POINTER(MeshDesc), vp, C.POINTER(vp)]),
+        "fo_mesh_destroy": (None, [vp]),
+        "fo_mesh_info": (C.c_int, [vp, i64p, i64p, i64p, i64p]),
+        "fo_jacobian_pattern": (C.c_int, [vp, vp, vp, vp]),
+        "fo_assemble_residual": (C.c_int, [vp, vp, vp, vp]),
+        "fo_assemble_jacobian": (C.c_int, [vp, vp, vp, vp, i32, i32, vp]),
+        "fo_initial_guess_sia": (C.c_int, [vp, vp, vp]),
+        "fo_profile_enable": (C.c_int, [vp, i32]),
+        "fo_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), i64p]),
+        "fo_status_string": (C.c_char_p, [C.c_int]),
+        "fo_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    for name, (res, args) in EXTRA_SIGNATURES.items():
+        if hasattr(lib, name):
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+
+
+# entry points added by later parts of the library (declared when present)
+EXTRA_SIGNATURES: dict = {}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2204_04321_amd.build`")
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def check(status: int):
+    if status != FO_OK:
+        L = lib()
+        raise FoError(status, L.fo_last_error().decode() or L.fo_status_string(status).decode())

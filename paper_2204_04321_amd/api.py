@@ -1,0 +1,128 @@
+"""Python binding over the C ABI: marshals arrays and PyTorch device tensors into
+library calls.  Every step of the computation runs in the HIP library; PyTorch
+only supplies device memory and the current stream."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FO_F32, FO_F64, FO_HEX8, FO_JAC_NEWTON, FO_JAC_PICARD, FO_WEDGE6, check
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return int(t.data_ptr())
+
+
+class Mesh:
+    """An uploaded extruded mesh.  `desc` is any object with the fields elem ('wedge' or
+    'hex'), xy [V,2], cells [T,3|4], surface, thickness, beta [V], sigma [L+1], and the
+    constants A, n, rho, g, eps0."""
+
+    def __init__(self, desc, stream=None):
+        L = _lib.lib()
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a.ctypes.data
+
+        elem = FO_WEDGE6 if desc.elem == "wedge" else FO_HEX8
+        d = _lib.MeshDesc()
+        d.elem = elem
+        d.n_base_verts = int(desc.xy.shape[0])
+        d.n_base_cells = int(desc.cells.shape[0])
+        d.n_layers = int(len(desc.sigma) - 1)
+        d.base_xy = arr(desc.xy, np.float64)
+        d.base_cells = arr(desc.cells, np.int32)
+        d.surface = arr(desc.surface, np.float64)
+        d.thickness = arr(desc.thickness, np.float64)
+        d.beta = arr(desc.beta, np.float64)
+        d.sigma = arr(desc.sigma, np.float64)
+        d.A, d.n, d.rho, d.g, d.eps0 = (float(desc.A), float(desc.n), float(desc.rho),
+                                         float(desc.g), float(desc.eps0))
+        h = C.c_void_p()
+        check(L.fo_mesh_create(C.byref(d), _stream(stream), C.byref(h)))
+        self._keep = []
+        self.handle = h
+        nn, nd, nc, nz = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        check(L.fo_mesh_info(h, C.byref(nn), C.byref(nd), C.byref(nc), C.byref(nz)))
+        self.n_nodes, self.n_dofs, self.n_cells, self.nnz = nn.value, nd.value, nc.value, nz.value
+        self.elem = desc.elem
+        self.n_layers = int(len(desc.sigma) - 1)
+        self.n_verts = int(desc.xy.shape[0])
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lib().fo_mesh_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- pattern ---------------------------------------------------------------------------
+    def pattern(self, stream=None):
+        rowptr = torch.empty(self.n_dofs + 1, dtype=torch.int64, device=self.device)
+        colidx = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        check(_lib.lib().fo_jacobian_pattern(self.handle, _ptr(rowptr), _ptr(colidx), _stream(stream)))
+        return rowptr, colidx
+
+    # ---- assembly --------------------------------------------------------------------------
+    def residual(self, U: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        self._check_vec(U)
+        R = out if out is not None else torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        check(_lib.lib().fo_assemble_residual(self.handle, _ptr(U), _ptr(R), _stream(stream)))
+        return R
+
+    def jacobian(self, U: torch.Tensor, dtype: str = "f64", kind: str = "newton",
+                 with_residual: bool = True, Jvals: torch.Tensor | None = None,
+                 R: torch.Tensor | None = None, stream=None):
+        self._check_vec(U)
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        if Jvals is None:
+            Jvals = torch.empty(self.nnz, dtype=tdt, device=self.device)
+        if with_residual and R is None:
+            R = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        check(_lib.lib().fo_assemble_jacobian(
+            self.handle, _ptr(U), _ptr(R) if with_residual else None, _ptr(Jvals),
+            FO_F64 if dtype == "f64" else FO_F32,
+            FO_JAC_NEWTON if kind == "newton" else FO_JAC_PICARD, _stream(stream)))
+        return (R, Jvals) if with_residual else Jvals
+
+    def sia(self, out: torch.Tensor | None = None, stream=None):
+        U = out if out is not None else torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        check(_lib.lib().fo_initial_guess_sia(self.handle, _ptr(U), _stream(stream)))
+        return U
+
+    # ---- measurement ----------------------------------------------------------------------
+    def profile(self, on: bool = True):
+        check(_lib.lib().fo_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self):
+        """(summed assembly-kernel milliseconds, launches) since the last read."""
+        ms, n = C.c_double(), C.c_int64()
+        check(_lib.lib().fo_profile_read(self.handle, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def _check_vec(self, U):
+        if U.dtype != torch.float64 or U.numel() != self.n_dofs:
+            raise ValueError(f"expected float64 vector of {self.n_dofs} dofs")

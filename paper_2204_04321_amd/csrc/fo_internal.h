@@ -1,0 +1,94 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fo_stokes.h"
+
+namespace fo {
+
+// Thread-local error message behind fo_last_error().
+void set_error(const std::string &msg);
+fo_status fail(fo_status s, const std::string &msg);
+
+#define FO_HIP_TRY(expr)                                                               \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return ::fo::fail(FO_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+#define FO_LAUNCH_CHECK(what)                                                          \
+  do {                                                                                 \
+    hipError_t _e = hipGetLastError();                                                 \
+    if (_e != hipSuccess)                                                              \
+      return ::fo::fail(FO_EDEVICE, std::string(what " launch failed: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+// Device-side view of one extruded mesh (plain pointers; passed by value to kernels).
+struct MeshView {
+  int32_t nv;        // vertices per base cell: 3 (wedge) or 4 (hex)
+  int32_t L;         // layers
+  int32_t V;         // base vertices
+  int32_t T;         // base cells
+  int64_t n_cells;   // T * L
+  int64_t n_dofs;    // 2 * V * (L + 1)
+  const double4 *geo;      // [V] x, y, bed = s - H, H
+  const double2 *sb;       // [V] s, beta
+  const int64_t *colptr;   // [V + 1] first CSR entry of each vertex column's row block
+  const int32_t *deg;      // [V] neighbouring columns including itself
+  const int32_t *cells;    // [T * nv]
+  const uint8_t *rank;     // [T * nv * nv] rank[a][b]: position of vertex b in a's neighbour list
+  const double *sigma;     // [L + 1]
+  double rho_g;            // rho * g
+  double visc_pref;        // 1/2 A^(-1/n)
+  double visc_exp;         // (1 - n) / (2 n)
+  double n_glen;
+  double A;
+  double eps0_sq;
+};
+
+}  // namespace fo
+
+struct fo_mesh {
+  fo::MeshView view;
+  int32_t elem;
+  int64_t nnz;
+  // device allocations owned by the mesh
+  double4 *geo = nullptr;
+  double2 *sb = nullptr;
+  int64_t *colptr = nullptr;
+  int32_t *deg = nullptr;
+  int32_t *cells = nullptr;
+  uint8_t *rank = nullptr;
+  double *sigma = nullptr;
+  int32_t *nbr_ptr = nullptr;   // [V + 1] sorted neighbour lists (incl. self)
+  int32_t *nbr_idx = nullptr;
+  int32_t *self_rank = nullptr; // [V] position of each vertex in its own neighbour list
+  int32_t *vc_ptr = nullptr;    // [V + 1] base cells around each vertex
+  int32_t *vc_idx = nullptr;
+  int64_t *rowptr = nullptr;    // [n_dofs + 1]
+  int32_t *colidx = nullptr;    // [nnz]
+  int device = 0;
+  // optional kernel timing (fo_profile_enable / fo_profile_read)
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t n_recorded = 0;
+};
+
+namespace fo {
+// Kernel launchers (fo_assemble.hip, fo_mesh_kernels.hip)
+fo_status launch_pattern(const fo_mesh *m, hipStream_t s);
+fo_status launch_assemble(const fo_mesh *m, const double *U, double *R, void *J, int dtype,
+                          int kind, bool want_jac, hipStream_t s);
+fo_status launch_sia(const fo_mesh *m, double *U, hipStream_t s);
+fo_status launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// kernel timing brackets (no-ops unless profiling is enabled on the mesh)
+fo_status profile_begin(const fo_mesh *m, hipStream_t s);
+fo_status profile_end(const fo_mesh *m, hipStream_t s);
+}  // namespace fo

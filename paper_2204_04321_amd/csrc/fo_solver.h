@@ -1,0 +1,19 @@
+// Launchers of the linear-algebra kernels used by the Newton driver.
+#pragma once
+
+#include "fo_internal.h"
+
+namespace fo {
+fo_status spmv(const fo_mesh *mesh, const void *vals, int dtype, const double *x, double *y, hipStream_t s);
+fo_status colblock_factor(const fo_mesh *mesh, const void *vals, int dtype, double *fac, hipStream_t s);
+fo_status colblock_apply(const fo_mesh *mesh, const double *fac, const double *r, double *z, hipStream_t s);
+int multidot_blocks(int64_t n);
+// out[0..nv-1] = V_i . w, out[nv] = w . w (partial: multidot_blocks(n) * (nv + 1) doubles)
+fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double *w, double *partial,
+                   double *out, hipStream_t s);
+// w += sign * sum_i h_i V_i
+fo_status multiaxpy(int64_t n, const double *V, int64_t ld, int nv, const double *h, double *w, double sign,
+                    hipStream_t s);
+fo_status axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+fo_status xpay(int64_t n, const double *x, double a, const double *y, double *z, hipStream_t s);
+}  // namespace fo
