@@ -295,14 +295,17 @@ def residual(mesh, U, **kw):
     return assemble(mesh, U, want_jac=False, **kw)[0]
 
 
-def abs_scales(mesh, U, picard=False, chunk=20000):
-    """Row scales sum_e |R_e,i| and max_j sum_e |J_e,ij| used to judge rounding-level parity."""
+def abs_scales(mesh, U, picard=False, chunk=20000, cells=None):
+    """Row scales sum_e |R_e,i| and max_j sum_e |J_e,ij| used to judge rounding-level parity
+    (optionally from a subset of cells: exact for rows whose cells are all included)."""
     ref = RefElement(mesh.elem)
     xyz = node_xyz(mesh)
     nd = mesh.n_dofs
     rs = np.zeros(nd)
     Jabs = None
-    for ids in _chunks(mesh.n_cells, chunk):
+    all_cells = np.arange(mesh.n_cells) if cells is None else np.asarray(cells)
+    for ch in _chunks(all_cells.shape[0], chunk):
+        ids = all_cells[ch]
         Re, Je, nodes = element_arrays(mesh, ids, U, ref, True, picard, xyz)
         dofs = (2 * nodes[:, :, None] + np.arange(2)[None, None, :]).reshape(ids.shape[0], -1)
         rs += np.bincount(dofs.ravel(), weights=np.abs(Re).reshape(-1), minlength=nd)
