@@ -4,22 +4,27 @@
 // strain-rate vectors eps1 = (2 e_xx + e_yy, e_xy, e_xz), eps2 = (e_xy,
 // e_xx + 2 e_yy, e_yz); Glen viscosity eq. (effvisc) with the effective strain
 // rate eq. (effeps), regularised by eps0; stress-free surface; linear bed
-// friction beta u.  Discrete residual eq. (residual), Jacobian eq. (linearsystem)
-// by forward-mode AD (Sec. 3.2): one derivative direction per element dof.
+// friction beta u.  Discrete residual eq. (residual); Jacobian eq. (linearsystem)
+// by forward-mode AD (Sec. 3.2): the tangent of the element residual along each
+// element dof is pushed through strain rate -> eps_e^2 -> mu -> residual.
 //
-// Work decomposition (one "team" of 16 lanes per cell, 4 cells per wave64):
-//   gather   every lane of the team reads the cell's nodal data (same addresses);
-//   primal   lane q < NQ evaluates quadrature point q: geometry, basis gradients,
-//            strain rates, viscosity and its derivative; results go to LDS;
-//   tangents lane j < NDOF is derivative lane j: it seeds dU = e_j and pushes the
-//            tangent through strain rate -> eps_e^2 -> mu -> element residual,
-//            producing column j of the element Jacobian (and residual entry j);
-//   scatter  lane j adds its residual entry and Jacobian column into the CSR
-//            values with hardware FP64/FP32 atomics.
-// Slots in the CSR are computed arithmetically from the column-major numbering:
-// row (vertex a, level kr, comp c) starts at colptr[a] + 4 D_a cumlev(kr)
-// + c 2 nlev(kr) D_a; column (vertex b, level kc, comp d) sits at
-// rank(a,b) 2 nlev(kr) + 2 (kc - max(kr-1, 0)) + d within it.
+// Owner-computes decomposition.  Every CSR row block belongs to one vertex column
+// v (all dofs of v, every level).  Work item = (v, base cell t around v): one lane
+// walks the column of t from the bed up, layer by layer, and evaluates each cell
+// at its quadrature points (geometry, strain rate, viscosity: the primal), then
+// the residual rows of v's two nodes in the cell and their derivatives along all
+// element dofs (the AD tangents, one register accumulator per derivative
+// direction and row).  A wave owns a run of consecutive vertex columns (<= 64
+// items); its lanes add their rows into a two-level window of those columns in
+// LDS, and once level k has received both cells that touch it (layers k-1 and k)
+// the wave copies it into its contiguous CSR range.  No global atomics, no
+// zero fill of J or R, every value written once; results do not depend on
+// scheduling.  Each cell is evaluated by each of its vertex columns (3 or 4
+// times) in exchange.
+//
+// CSR slot of row (v, level kr, comp c) and column (vertex of rank r in v's sorted
+// neighbour list, level kc, comp d): colptr[v] + 4 D_v cumlev(kr) + c 2 nlev(kr) D_v
+// + r 2 nlev(kr) + 2 (kc - max(kr-1, 0)) + d.
 #include <hip/hip_runtime.h>
 
 #include "fo_internal.h"
@@ -27,9 +32,7 @@
 namespace fo {
 namespace {
 
-constexpr int TEAM = 16;
-constexpr int BLOCK = 256;
-constexpr int TEAMS_PER_BLOCK = BLOCK / TEAM;
+constexpr int WAVE = 64;
 
 constexpr double G1 = 0.21132486540518711775;   // 1/2 - 1/(2 sqrt 3)
 constexpr double G2 = 0.78867513459481288225;   // 1/2 + 1/(2 sqrt 3)
@@ -38,50 +41,27 @@ template <int NV>
 struct Elem;
 template <>
 struct Elem<3> {  // wedge: P1 triangle x linear in zeta
-  static constexpr int NPE = 6, NDOF = 12, NQ = 6, NQB = 3;
+  static constexpr int NPE = 6, NQ = 6, NQB = 3;
 };
 template <>
 struct Elem<4> {  // hexahedron: bilinear quad x linear in zeta
-  static constexpr int NPE = 8, NDOF = 16, NQ = 8, NQB = 4;
+  static constexpr int NPE = 8, NQ = 8, NQB = 4;
 };
 
-// Reference quadrature point q (reference cell [0,1]^2 or unit triangle, zeta in [0,1]).
-template <int NV>
-__device__ __forceinline__ void qpoint(int q, double &xi, double &eta, double &zeta, double &w) {
-  if constexpr (NV == 3) {
-    const int t = q % 3;
-    xi = (t == 1) ? 2.0 / 3.0 : 1.0 / 6.0;
-    eta = (t == 2) ? 2.0 / 3.0 : 1.0 / 6.0;
-    zeta = (q < 3) ? G1 : G2;
-    w = 1.0 / 12.0;
-  } else {
-    xi = (q & 1) ? G2 : G1;
-    eta = (q & 2) ? G2 : G1;
-    zeta = (q & 4) ? G2 : G1;
-    w = 0.125;
-  }
-}
+// Quadrature on the reference cell ([0,1]^2 or the unit triangle, zeta in [0,1]):
+// weights, zeta, 2D basis values and reference derivatives at each point.
+struct QTable {
+  double w[8], zeta[8], lam[8][4], dlx[8][4], dly[8][4];
+  double bw[4], blam[4][4], bdlx[4][4], bdly[4][4];
+};
 
-template <int NV>
-__device__ __forceinline__ void bpoint(int r, double &xi, double &eta, double &w) {
-  if constexpr (NV == 3) {
-    xi = (r == 1) ? 2.0 / 3.0 : 1.0 / 6.0;
-    eta = (r == 2) ? 2.0 / 3.0 : 1.0 / 6.0;
-    w = 1.0 / 6.0;
-  } else {
-    xi = (r & 1) ? G2 : G1;
-    eta = (r & 2) ? G2 : G1;
-    w = 0.25;
-  }
-}
+__constant__ QTable kQ[2];   // [0] wedge, [1] hex
 
-// 2D basis values and reference derivatives.
-template <int NV>
-__device__ __forceinline__ void basis2d(double xi, double eta, double *lam, double *dx, double *dy) {
-  if constexpr (NV == 3) {
-    lam[0] = 1.0 - xi - eta; lam[1] = xi; lam[2] = eta;
-    dx[0] = -1.0; dx[1] = 1.0; dx[2] = 0.0;
-    dy[0] = -1.0; dy[1] = 0.0; dy[2] = 1.0;
+constexpr void basis2d_tab(int nv, double xi, double eta, double *lam, double *dx, double *dy) {
+  if (nv == 3) {
+    lam[0] = 1.0 - xi - eta; lam[1] = xi; lam[2] = eta; lam[3] = 0.0;
+    dx[0] = -1.0; dx[1] = 1.0; dx[2] = 0.0; dx[3] = 0.0;
+    dy[0] = -1.0; dy[1] = 0.0; dy[2] = 1.0; dy[3] = 0.0;
   } else {
     const double mx = 1.0 - xi, my = 1.0 - eta;
     lam[0] = mx * my; lam[1] = xi * my; lam[2] = xi * eta; lam[3] = mx * eta;
@@ -90,228 +70,390 @@ __device__ __forceinline__ void basis2d(double xi, double eta, double *lam, doub
   }
 }
 
+constexpr QTable make_table(int nv) {
+  QTable t{};
+  const int nq = nv == 3 ? 6 : 8, nqb = nv == 3 ? 3 : 4;
+  for (int q = 0; q < nq; ++q) {
+    double xi = 0, eta = 0, zeta = 0, w = 0;
+    if (nv == 3) {
+      const int tq = q % 3;
+      xi = (tq == 1) ? 2.0 / 3.0 : 1.0 / 6.0;
+      eta = (tq == 2) ? 2.0 / 3.0 : 1.0 / 6.0;
+      zeta = (q < 3) ? G1 : G2;
+      w = 1.0 / 12.0;
+    } else {
+      xi = (q & 1) ? G2 : G1;
+      eta = (q & 2) ? G2 : G1;
+      zeta = (q & 4) ? G2 : G1;
+      w = 0.125;
+    }
+    t.w[q] = w;
+    t.zeta[q] = zeta;
+    basis2d_tab(nv, xi, eta, t.lam[q], t.dlx[q], t.dly[q]);
+  }
+  for (int r = 0; r < nqb; ++r) {
+    double xi = 0, eta = 0;
+    if (nv == 3) {
+      xi = (r == 1) ? 2.0 / 3.0 : 1.0 / 6.0;
+      eta = (r == 2) ? 2.0 / 3.0 : 1.0 / 6.0;
+      t.bw[r] = 1.0 / 6.0;
+    } else {
+      xi = (r & 1) ? G2 : G1;
+      eta = (r & 2) ? G2 : G1;
+      t.bw[r] = 0.25;
+    }
+    basis2d_tab(nv, xi, eta, t.blam[r], t.bdlx[r], t.bdly[r]);
+  }
+  return t;
+}
+
 __device__ __forceinline__ int nlev(int k, int L) { return (k == 0 || k == L) ? 2 : 3; }
 __device__ __forceinline__ int cumlev(int k) { return k == 0 ? 0 : 3 * k - 1; }
 
-template <class T>
-__device__ __forceinline__ void atomic_add(T *p, T v) {
-  unsafeAtomicAdd(p, v);
+// 1/x: hardware estimate refined by two Newton steps (full double precision).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
 }
 
-// Per quadrature point record in LDS (doubles): grad N_a (3 NPE), g_(a,c) = eps_c . grad N_a
-// (2 NPE), then 2 mu W, 2 mu' W, W rho g s_x, W rho g s_y.
-template <int NV>
-struct Rec {
-  static constexpr int NPE = Elem<NV>::NPE;
-  static constexpr int GN = 0, GV = 3 * NPE, S2 = 5 * NPE, T2 = S2 + 1, GX = S2 + 2, GY = S2 + 3;
-  static constexpr int SIZE = 5 * NPE + 4;
-  // reduced-precision copy for FP32 derivative lanes: grad N, g, 2 mu W, 2 mu' W
-  static constexpr int FSIZE = 5 * NPE + 2;
-};
+// x^(-1/3) for x > 0: single-precision exp2/log2 estimate (~1e-7) refined by two Newton
+// steps on y^-3 = x, y <- y (4 - x y^3) / 3 (quadratic convergence to double precision).
+__device__ __forceinline__ double rcbrt64(double x) {
+  double y = double(__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(float(x)) * (1.0f / 3.0f)));
+  y = y * (4.0 - x * (y * y * y)) * (1.0 / 3.0);
+  y = y * (4.0 - x * (y * y * y)) * (1.0 / 3.0);
+  return y;
+}
 
-template <int NV, bool JAC, class JT>
-__global__ __launch_bounds__(BLOCK) void assemble_kernel(MeshView m, const double *__restrict__ U,
-                                                         double *__restrict__ R, JT *__restrict__ J,
-                                                         int picard) {
-  using E = Elem<NV>;
-  using RC = Rec<NV>;
-  constexpr int NPE = E::NPE, NDOF = E::NDOF, NQ = E::NQ, NQB = E::NQB;
-  constexpr bool F32 = JAC && sizeof(JT) == 4;
-  __shared__ double lds[TEAMS_PER_BLOCK * NQ * RC::SIZE];
-  __shared__ float ldsf[F32 ? TEAMS_PER_BLOCK * NQ * RC::FSIZE : 1];
+template <class T>
+__device__ __forceinline__ void lds_add(T *p, T v) {
+  atomicAdd(p, v);   // LDS atomics: lanes of one wave may hit the same entry
+}
 
-  const int team = threadIdx.x / TEAM;
-  const int lane = threadIdx.x % TEAM;
-  const int64_t cell = int64_t(blockIdx.x) * TEAMS_PER_BLOCK + team;
-  const bool active = cell < m.n_cells;
+// The block is one wave: a workgroup barrier orders its LDS traffic.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <class T>
+__device__ __forceinline__ T sel4(int i, T a, T b, T c, T d) {
+  return i == 0 ? a : (i == 1 ? b : (i == 2 ? c : d));
+}
+
+// One wave = one task (a run of vertex columns); one lane = one (v, t) item.
+// N3 selects the n = 3 viscosity power; JAC adds the Jacobian; JT is its value type
+// (double, or float with FP32 derivative arithmetic over the FP64 primal).
+template <int NV, bool JAC, class JT, bool N3>
+__global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__restrict__ tasks,
+                                                     const double *__restrict__ U, double *__restrict__ R,
+                                                     JT *__restrict__ J, int picard, int max_slot,
+                                                     int max_tv) {
+  constexpr int NQ = Elem<NV>::NQ, NQB = Elem<NV>::NQB;
+  using AT = JT;   // derivative arithmetic type
+  const QTable &Q = kQ[NV == 3 ? 0 : 1];
+  extern __shared__ __align__(16) unsigned char smem[];
+  JT *Jw = reinterpret_cast<JT *>(smem);                                                     // [2][max_slot]
+  double *Rw = reinterpret_cast<double *>(smem + (JAC ? 2 * size_t(max_slot) * sizeof(JT) : 0));  // [2][2 max_tv]
+
+  const int lane = threadIdx.x;
+  const int4 task = tasks[blockIdx.x];
+  const int vb = task.y, ve = task.z, ib = task.w;
+  const int ie = m.vc_ptr[ve];
+  const bool act = ib + lane < ie;
+  const int item = act ? ib + lane : ib;
   const int L = m.L;
-  const int64_t c = active ? cell : 0;
-  const int t = int(c / L);
-  const int k = int(c - int64_t(t) * L);
+  const int v = act ? m.item_vtx[item] : vb;
+  const int t = act ? m.vc_idx[item] : 0;
+  const int al = act ? m.vc_pos[item] : 0;
+  const int Dv = m.deg[v];
+  const int soff = m.slot_off[v];
+  const int rloc = 2 * (v - vb);
+  const int slot_size = m.slot_off[ve - 1] + 12 * m.deg[ve - 1];
 
-  // ---- gather (all lanes of the team, identical addresses) -----------------------------
-  int vid[NV];
-  double xl[NV], yl[NV], zb[NV], zt[NV], su[NV], bet[NV];
-  double uu[NPE], vv[NPE];
-  const double sk = m.sigma[k], sk1 = m.sigma[k + 1];
-  double x0 = 0.0, y0 = 0.0;
+  // ---- per-item constants -----------------------------------------------------------------
+  int vid[NV], rk[NV];
+  double xl[NV], yl[NV], bed[NV], Hh[NV], su[NV];
+  // horizontal coordinates relative to the cell's first corner, the bed, H and s
+  auto load_geo = [&](double *xl_, double *yl_, double *bed_, double *H_, double *s_) {
+    double x0 = 0, y0 = 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const double4 g = m.geo[vid[i]];
+      if (i == 0) { x0 = g.x; y0 = g.y; }
+      xl_[i] = g.x - x0;
+      yl_[i] = g.y - y0;
+      bed_[i] = g.z;
+      H_[i] = g.w;
+      s_[i] = m.sb[vid[i]].x;
+    }
+  };
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     vid[i] = m.cells[int64_t(t) * NV + i];
-    const double4 gm = m.geo[vid[i]];
-    const double2 sbv = m.sb[vid[i]];
-    if (i == 0) { x0 = gm.x; y0 = gm.y; }
-    xl[i] = gm.x - x0;              // local coordinates: differences of large numbers once
-    yl[i] = gm.y - y0;
-    zb[i] = gm.z + sk * gm.w;
-    zt[i] = gm.z + sk1 * gm.w;
-    su[i] = sbv.x;
-    bet[i] = sbv.y;
-    const int64_t nb = int64_t(vid[i]) * (L + 1) + k;
-    const double2 ub = *reinterpret_cast<const double2 *>(U + 2 * nb);
-    const double2 ut = *reinterpret_cast<const double2 *>(U + 2 * nb + 2);
-    uu[i] = ub.x; vv[i] = ub.y;
-    uu[NV + i] = ut.x; vv[NV + i] = ut.y;
+    rk[i] = m.rank[(int64_t(t) * NV + al) * NV + i];
+  }
+  load_geo(xl, yl, bed, Hh, su);
+  // P1 triangles: the horizontal basis gradients and the map determinant are constant
+  double lxc[NV], lyc[NV], detc = 0, sxc = 0, syc = 0;
+  if constexpr (NV == 3) {
+    const double x_xi = xl[1] - xl[0], x_eta = xl[2] - xl[0];
+    const double y_xi = yl[1] - yl[0], y_eta = yl[2] - yl[0];
+    detc = x_xi * y_eta - x_eta * y_xi;
+    const double iG = rcp64(detc);
+    lxc[1] = y_eta * iG; lxc[2] = -y_xi * iG; lxc[0] = -(lxc[1] + lxc[2]);
+    lyc[1] = -x_eta * iG; lyc[2] = x_xi * iG; lyc[0] = -(lyc[1] + lyc[2]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) { sxc += su[i] * lxc[i]; syc += su[i] * lyc[i]; }
+  }
+  double lx_al = 0.0, ly_al = 0.0;
+  if constexpr (NV == 3) {
+    lx_al = sel4(al, lxc[0], lxc[1], lxc[2], 0.0);
+    ly_al = sel4(al, lyc[0], lyc[1], lyc[2], 0.0);
   }
 
-  double *rec = lds + team * NQ * RC::SIZE;
-  float *recf = ldsf + (F32 ? team * NQ * RC::FSIZE : 0);
+  // ---- zero both level windows -------------------------------------------------------------
+  if constexpr (JAC) {
+    for (int e = lane; e < slot_size; e += WAVE) { Jw[e] = JT(0); Jw[max_slot + e] = JT(0); }
+  }
+  for (int e = lane; e < 2 * (ve - vb); e += WAVE) { Rw[e] = 0.0; Rw[2 * max_tv + e] = 0.0; }
 
-  // ---- primal: lane q evaluates quadrature point q ----------------------------------------
-  if (lane < NQ) {
-    double xi, eta, zeta, w;
-    qpoint<NV>(lane, xi, eta, zeta, w);
-    double lam[NV], dlx[NV], dly[NV];
-    basis2d<NV>(xi, eta, lam, dlx, dly);
-    const double l0 = 1.0 - zeta, l1 = zeta;
-    double x_xi = 0, x_eta = 0, y_xi = 0, y_eta = 0, z_xi = 0, z_eta = 0, z_ze = 0;
+  // level-k nodal data of the cell's vertices (carried up the column)
+  double zlo[NV], ulo[NV], vlo[NV];
+  {
+    const double s0 = m.sigma[0];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const double zc = l0 * zb[i] + l1 * zt[i];
-      x_xi += xl[i] * dlx[i]; x_eta += xl[i] * dly[i];
-      y_xi += yl[i] * dlx[i]; y_eta += yl[i] * dly[i];
-      z_xi += zc * dlx[i];    z_eta += zc * dly[i];
-      z_ze += lam[i] * (zt[i] - zb[i]);
-    }
-    const double detG = x_xi * y_eta - x_eta * y_xi;
-    const double iG = 1.0 / detG;
-    const double i00 = y_eta * iG, i01 = -x_eta * iG, i10 = -y_xi * iG, i11 = x_xi * iG;
-    const double izz = 1.0 / z_ze;
-    const double zx = -(z_xi * i00 + z_eta * i10) * izz;   // d zeta / dx
-    const double zy = -(z_xi * i01 + z_eta * i11) * izz;   // d zeta / dy
-    const double W = w * detG * z_ze;
-    double gx[NPE], gy[NPE], gz[NPE];
-    double ux = 0, uy = 0, uz = 0, vx = 0, vy = 0, vz = 0, sx = 0, sy = 0;
-#pragma unroll
-    for (int a = 0; a < NPE; ++a) {
-      const int i = a % NV;
-      const double ll = (a < NV) ? l0 : l1;
-      const double dl = (a < NV) ? -1.0 : 1.0;
-      const double nxi = dlx[i] * ll, neta = dly[i] * ll, nze = lam[i] * dl;
-      gx[a] = nxi * i00 + neta * i10 + nze * zx;
-      gy[a] = nxi * i01 + neta * i11 + nze * zy;
-      gz[a] = nze * izz;
-      ux += uu[a] * gx[a]; uy += uu[a] * gy[a]; uz += uu[a] * gz[a];
-      vx += vv[a] * gx[a]; vy += vv[a] * gy[a]; vz += vv[a] * gz[a];
-      sx += su[i] * gx[a]; sy += su[i] * gy[a];
-    }
-    const double exx = ux, eyy = vy, exy = 0.5 * (uy + vx), exz = 0.5 * uz, eyz = 0.5 * vz;
-    const double q = exx * exx + eyy * eyy + exx * eyy + exy * exy + exz * exz + eyz * eyz;
-    const double qe = q + m.eps0_sq;
-    const double mu = m.visc_pref * pow(qe, m.visc_exp);
-    const double dmu = m.visc_exp * mu / qe;
-    const double e1x = 2.0 * exx + eyy, e1y = exy, e1z = exz;
-    const double e2x = exy, e2y = exx + 2.0 * eyy, e2z = eyz;
-    double *P = rec + lane * RC::SIZE;
-#pragma unroll
-    for (int a = 0; a < NPE; ++a) {
-      P[RC::GN + 3 * a + 0] = gx[a];
-      P[RC::GN + 3 * a + 1] = gy[a];
-      P[RC::GN + 3 * a + 2] = gz[a];
-      P[RC::GV + 2 * a + 0] = e1x * gx[a] + e1y * gy[a] + e1z * gz[a];
-      P[RC::GV + 2 * a + 1] = e2x * gx[a] + e2y * gy[a] + e2z * gz[a];
-    }
-    P[RC::S2] = 2.0 * mu * W;
-    P[RC::T2] = picard ? 0.0 : 2.0 * dmu * W;
-    P[RC::GX] = W * m.rho_g * sx;
-    P[RC::GY] = W * m.rho_g * sy;
-    if constexpr (F32) {
-      float *Pf = recf + lane * RC::FSIZE;
-#pragma unroll
-      for (int i = 0; i < 5 * NPE + 2; ++i) Pf[i] = float(P[i]);
+      zlo[i] = bed[i] + s0 * Hh[i];
+      const double2 uv = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1)));
+      ulo[i] = uv.x; vlo[i] = uv.y;
     }
   }
-  __syncthreads();
+  wave_sync();
 
-  // ---- tangents: lane j = element dof (b, d) ---------------------------------------------
-  const int j = lane;
-  const int b = j >> 1, d = j & 1;
-  const bool jlane = active && j < NDOF;
-  const int bj = jlane ? b : 0;
-  using AT = typename std::conditional<F32, float, double>::type;
-  double res = 0.0;
-  AT col[NDOF];
+  for (int k = 0; k < L; ++k) {
+    const int cur = k & 1, nxt = cur ^ 1;
+    // gather level k+1 as increments over level k
+    double dz[NV], du[NV], dv[NV];
+    const double s1 = m.sigma[k + 1];
 #pragma unroll
-  for (int i = 0; i < NDOF; ++i) col[i] = AT(0);
+    for (int i = 0; i < NV; ++i) {
+      dz[i] = (bed[i] + s1 * Hh[i]) - zlo[i];
+      const double2 uv = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1) + k + 1));
+      du[i] = uv.x - ulo[i];
+      dv[i] = uv.y - vlo[i];
+    }
+
+    // residual rows of v's lower (index 0) and upper (index 1) node, and their tangents:
+    // Jx[a][c][d][j][lev] = d R_(a,c) / d U_(node (j, lev), d)
+    double Rb0 = 0, Rb1 = 0, Rt0 = 0, Rt1 = 0;
+    AT Jx[2][2][2][NV][2];
+    if constexpr (JAC) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int j = 0; j < NV; ++j) { Jx[a][c][d][j][0] = AT(0); Jx[a][c][d][j][1] = AT(0); }
+    }
 
 #pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    const double *P = rec + q * RC::SIZE;
-    double xi, eta, zeta, w;
-    qpoint<NV>(q, xi, eta, zeta, w);
-    double lam[NV], dlx[NV], dly[NV];
-    basis2d<NV>(xi, eta, lam, dlx, dly);
-    const double Nb = lam[bj % NV] * ((bj < NV) ? (1.0 - zeta) : zeta);
-    const double gbd = P[RC::GV + 2 * bj + d];
-    res += P[RC::S2] * gbd + P[RC::GX + d] * Nb;
-    if constexpr (JAC) {
-      const AT *Q;
-      if constexpr (F32) Q = recf + q * RC::FSIZE; else Q = P;
-      const AT bx = Q[RC::GN + 3 * bj], by = Q[RC::GN + 3 * bj + 1], bz = Q[RC::GN + 3 * bj + 2];
-      const AT s2 = Q[RC::S2];
-      const AT tg = Q[RC::T2] * Q[RC::GV + 2 * bj + d];     // d(2 mu W) along e_j
-      // tangent of eps1 / eps2 along e_j, scaled by 2 mu W
-      const AT h = AT(0.5), two = AT(2);
-      AT p1x, p1y, p1z, p2x, p2y, p2z;
-      if (d == 0) { p1x = two * bx; p1y = h * by; p1z = h * bz; p2x = h * by; p2y = bx; p2z = AT(0); }
-      else        { p1x = by; p1y = h * bx; p1z = AT(0); p2x = h * bx; p2y = two * by; p2z = h * bz; }
-      p1x *= s2; p1y *= s2; p1z *= s2; p2x *= s2; p2y *= s2; p2z *= s2;
+    for (int q = 0; q < NQ; ++q) {
+      const double zeta = Q.zeta[q], l0 = 1.0 - zeta, l1 = zeta;
+      double lam[NV], lx[NV], ly[NV];
+      double det, sx, sy;
 #pragma unroll
-      for (int a = 0; a < NPE; ++a) {
-        const AT ax = Q[RC::GN + 3 * a], ay = Q[RC::GN + 3 * a + 1], az = Q[RC::GN + 3 * a + 2];
-        col[2 * a] += ax * p1x + ay * p1y + az * p1z + tg * Q[RC::GV + 2 * a];
-        col[2 * a + 1] += ax * p2x + ay * p2y + az * p2z + tg * Q[RC::GV + 2 * a + 1];
+      for (int i = 0; i < NV; ++i) lam[i] = Q.lam[q][i];
+      if constexpr (NV == 3) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) { lx[i] = lxc[i]; ly[i] = lyc[i]; }
+        det = detc; sx = sxc; sy = syc;
+      } else {
+        double x_xi = 0, x_eta = 0, y_xi = 0, y_eta = 0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          x_xi += xl[i] * Q.dlx[q][i]; x_eta += xl[i] * Q.dly[q][i];
+          y_xi += yl[i] * Q.dlx[q][i]; y_eta += yl[i] * Q.dly[q][i];
+        }
+        det = x_xi * y_eta - x_eta * y_xi;
+        const double iG = rcp64(det);
+        const double i00 = y_eta * iG, i01 = -x_eta * iG, i10 = -y_xi * iG, i11 = x_xi * iG;
+        sx = 0; sy = 0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          lx[i] = Q.dlx[q][i] * i00 + Q.dly[q][i] * i10;
+          ly[i] = Q.dlx[q][i] * i01 + Q.dly[q][i] * i11;
+          sx += su[i] * lx[i];
+          sy += su[i] * ly[i];
+        }
       }
-    }
-  }
-
-  // ---- bed friction on the lower face of bottom-layer cells -------------------------------
-  if (k == 0) {
-#pragma unroll
-    for (int r = 0; r < NQB; ++r) {
-      double xi, eta, w;
-      bpoint<NV>(r, xi, eta, w);
-      double lam[NV], dlx[NV], dly[NV];
-      basis2d<NV>(xi, eta, lam, dlx, dly);
-      double txx = 0, txy = 0, txz = 0, tyx = 0, tyy = 0, tyz = 0, br = 0, ur = 0;
+      // vertical map: z_zeta and the slopes of z along x, y at fixed zeta
+      double zze = 0, zxs = 0, zys = 0;
+      double ucx = 0, ucy = 0, vcx = 0, vcy = 0, dum = 0, dvm = 0;
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
-        txx += xl[i] * dlx[i]; txy += yl[i] * dlx[i]; txz += zb[i] * dlx[i];
-        tyx += xl[i] * dly[i]; tyy += yl[i] * dly[i]; tyz += zb[i] * dly[i];
-        br += bet[i] * lam[i];
-        ur += (d == 0 ? uu[i] : vv[i]) * lam[i];
+        const double zc = zlo[i] + zeta * dz[i];
+        const double uc = ulo[i] + zeta * du[i];
+        const double vc = vlo[i] + zeta * dv[i];
+        zze += lam[i] * dz[i];
+        zxs += lx[i] * zc; zys += ly[i] * zc;
+        ucx += lx[i] * uc; ucy += ly[i] * uc;
+        vcx += lx[i] * vc; vcy += ly[i] * vc;
+        dum += lam[i] * du[i]; dvm += lam[i] * dv[i];
       }
-      const double nx = txy * tyz - txz * tyy, ny = txz * tyx - txx * tyz, nz = txx * tyy - txy * tyx;
-      const double wb = w * sqrt(nx * nx + ny * ny + nz * nz) * br;
-      if (bj < NV) {
-        res += wb * ur * lam[bj];
-        if constexpr (JAC) {
+      const double iz = rcp64(zze);
+      const double px = -zxs * iz, py = -zys * iz;        // d zeta / dx, d zeta / dy
+      const double W = Q.w[q] * det * zze;
+      // velocity gradient, strain rates, viscosity
+      const double ux = ucx + px * dum, uy = ucy + py * dum, uz = iz * dum;
+      const double vx = vcx + px * dvm, vy = vcy + py * dvm, vz = iz * dvm;
+      const double exx = ux, eyy = vy, exy = 0.5 * (uy + vx), exz = 0.5 * uz, eyz = 0.5 * vz;
+      const double qq = exx * exx + eyy * eyy + exx * eyy + exy * exy + exz * exz + eyz * eyz;
+      const double qe = qq + m.eps0_sq;
+      double mu;
+      if constexpr (N3) mu = m.visc_pref * rcbrt64(qe);
+      else mu = m.visc_pref * pow(qe, m.visc_exp);
+      const double s2 = 2.0 * mu * W;
+      const double t2 = picard ? 0.0 : 2.0 * (m.visc_exp * mu * rcp64(qe)) * W;
+      const double e1x = 2.0 * exx + eyy, e1y = exy, e1z = exz;
+      const double e2x = exy, e2y = exx + 2.0 * eyy, e2z = eyz;
+      const double gvx = W * m.rho_g * sx, gvy = W * m.rho_g * sy;
+      // v's own nodes in this cell: corner al at the lower and upper level
+      const double lam_a = sel4(al, lam[0], lam[1], lam[2], lam[NV - 1]);
+      double lxa, lya;
+      if constexpr (NV == 3) { lxa = lx_al; lya = ly_al; }
+      else { lxa = sel4(al, lx[0], lx[1], lx[2], lx[NV - 1]); lya = sel4(al, ly[0], ly[1], ly[2], ly[NV - 1]); }
+      const double abx = l0 * lxa - lam_a * px, aby = l0 * lya - lam_a * py, abz = -lam_a * iz;
+      const double atx = l1 * lxa + lam_a * px, aty = l1 * lya + lam_a * py, atz = lam_a * iz;
+      const double gb0 = e1x * abx + e1y * aby + e1z * abz, gb1 = e2x * abx + e2y * aby + e2z * abz;
+      const double gt0 = e1x * atx + e1y * aty + e1z * atz, gt1 = e2x * atx + e2y * aty + e2z * atz;
+      Rb0 += s2 * gb0 + gvx * (lam_a * l0);
+      Rb1 += s2 * gb1 + gvy * (lam_a * l0);
+      Rt0 += s2 * gt0 + gvx * (lam_a * l1);
+      Rt1 += s2 * gt1 + gvy * (lam_a * l1);
+      if constexpr (JAC) {
+        // row side: 2 mu W times the row node's gradient (with the constant factors of
+        // d(eps_c . grad N_a)/dU), and 2 mu' W times its strain projection
+        AT RX[2][9];
+        {
+          const double ax[2] = {abx, atx}, ay[2] = {aby, aty}, az[2] = {abz, atz};
+          const double g0[2] = {gb0, gt0}, g1[2] = {gb1, gt1};
 #pragma unroll
-          for (int a = 0; a < NV; ++a) col[2 * a + d] += AT(wb * lam[a] * lam[bj]);
+          for (int a = 0; a < 2; ++a) {
+            const double Ax = s2 * ax[a], Ay = s2 * ay[a], Az = s2 * az[a];
+            RX[a][0] = AT(2.0 * Ax); RX[a][1] = AT(0.5 * Ay); RX[a][2] = AT(0.5 * Az);
+            RX[a][3] = AT(Ax);       RX[a][4] = AT(Ay);       RX[a][5] = AT(0.5 * Ax);
+            RX[a][6] = AT(2.0 * Ay); RX[a][7] = AT(t2 * g0[a]); RX[a][8] = AT(t2 * g1[a]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+#pragma unroll
+          for (int lev = 0; lev < 2; ++lev) {
+            const double ll = lev ? l1 : l0;
+            const double dl = lev ? lam[j] : -lam[j];
+            const double bxd = ll * lx[j] + dl * px, byd = ll * ly[j] + dl * py, bzd = dl * iz;
+            const AT bx = AT(bxd), by = AT(byd), bz = AT(bzd);
+            const AT gu = AT(e1x * bxd + e1y * byd + e1z * bzd);   // d(eps_e^2)/dU_(b,u)
+            const AT gv = AT(e2x * bxd + e2y * byd + e2z * bzd);   // d(eps_e^2)/dU_(b,v)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              Jx[a][0][0][j][lev] += RX[a][0] * bx + RX[a][1] * by + RX[a][2] * bz + RX[a][7] * gu;
+              Jx[a][0][1][j][lev] += RX[a][3] * by + RX[a][1] * bx + RX[a][7] * gv;
+              Jx[a][1][0][j][lev] += RX[a][4] * bx + RX[a][5] * by + RX[a][8] * gu;
+              Jx[a][1][1][j][lev] += RX[a][5] * bx + RX[a][6] * by + RX[a][2] * bz + RX[a][8] * gv;
+            }
+          }
         }
       }
     }
-  }
 
-  if (!jlane) return;
-  // ---- scatter -------------------------------------------------------------------------------
-  const int lev_b = b / NV, beta_v = b % NV;
-  const int kc = k + lev_b;
-  const int64_t node_b = int64_t(vid[beta_v]) * (L + 1) + kc;
-  if (R) atomic_add(R + 2 * node_b + d, res);
-  if constexpr (JAC) {
-    const uint8_t *rk = m.rank + int64_t(t) * NV * NV;
+    // ---- bed friction on the lower face of the bottom layer (uniform branch) -------------
+    if (k == 0) {
+      double bx_[NV], by_[NV], bb_[NV], bH_[NV], bs_[NV], be[NV];
+      load_geo(bx_, by_, bb_, bH_, bs_);
 #pragma unroll
-    for (int a = 0; a < NPE; ++a) {
-      const int al = a % NV, kr = k + a / NV;
-      const int va = vid[al];
-      const int Da = m.deg[va];
-      const int nl = nlev(kr, L);
-      const int64_t rowblk = m.colptr[va] + int64_t(4) * Da * cumlev(kr);
-      const int64_t off = int64_t(rk[al * NV + beta_v]) * 2 * nl + 2 * (kc - (kr > 0 ? kr - 1 : 0)) + d;
-      atomic_add(J + rowblk + off, JT(col[2 * a]));
-      atomic_add(J + rowblk + int64_t(2) * nl * Da + off, JT(col[2 * a + 1]));
+      for (int i = 0; i < NV; ++i) be[i] = m.sb[vid[i]].y;
+#pragma unroll
+      for (int r = 0; r < NQB; ++r) {
+        double txx = 0, txy = 0, txz = 0, tyx = 0, tyy = 0, tyz = 0, br = 0, ur = 0, vr = 0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          const double dx = Q.bdlx[r][i], dy = Q.bdly[r][i], lm = Q.blam[r][i];
+          txx += bx_[i] * dx; txy += by_[i] * dx; txz += zlo[i] * dx;
+          tyx += bx_[i] * dy; tyy += by_[i] * dy; tyz += zlo[i] * dy;
+          br += be[i] * lm; ur += ulo[i] * lm; vr += vlo[i] * lm;
+        }
+        const double nx = txy * tyz - txz * tyy, ny = txz * tyx - txx * tyz, nz = txx * tyy - txy * tyx;
+        const double wb = Q.bw[r] * sqrt(nx * nx + ny * ny + nz * nz) * br;
+        const double la = sel4(al, Q.blam[r][0], Q.blam[r][1], Q.blam[r][2], Q.blam[r][NV - 1]);
+        Rb0 += wb * ur * la;
+        Rb1 += wb * vr * la;
+        if constexpr (JAC) {
+#pragma unroll
+          for (int j = 0; j < NV; ++j) {
+            const AT f = AT(wb * la * Q.blam[r][j]);
+            Jx[0][0][0][j][0] += f;
+            Jx[0][1][1][j][0] += f;
+          }
+        }
+      }
     }
+
+    // ---- add v's rows into the level windows ------------------------------------------------
+    if (act) {
+      double *Rcur = Rw + cur * 2 * max_tv, *Rnxt = Rw + nxt * 2 * max_tv;
+      lds_add(Rcur + rloc, Rb0);
+      lds_add(Rcur + rloc + 1, Rb1);
+      lds_add(Rnxt + rloc, Rt0);
+      lds_add(Rnxt + rloc + 1, Rt1);
+      if constexpr (JAC) {
+        const int nlk = nlev(k, L), nl1 = nlev(k + 1, L);
+        const int offk = k > 0 ? 1 : 0;     // level k sits at window position 1 unless k = 0
+        JT *Wk = Jw + cur * max_slot + soff, *Wk1 = Jw + nxt * max_slot + soff;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int j = 0; j < NV; ++j)
+#pragma unroll
+            for (int lev = 0; lev < 2; ++lev)
+#pragma unroll
+              for (int d = 0; d < 2; ++d) {
+                lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, JT(Jx[0][c][d][j][lev]));
+                lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, JT(Jx[1][c][d][j][lev]));
+              }
+      }
+    }
+    wave_sync();
+
+    // ---- level k is complete: copy it to its CSR rows and clear it for level k+2 ------------
+    auto flush = [&](int lev_k, int slot) {
+      for (int u = vb; u < ve; ++u) {
+        const int Du = m.deg[u];
+        if constexpr (JAC) {
+          const int n = 4 * nlev(lev_k, L) * Du;
+          JT *src = Jw + slot * max_slot + m.slot_off[u];
+          JT *dst = J + m.colptr[u] + int64_t(4) * Du * cumlev(lev_k);
+          for (int e = lane; e < n; e += WAVE) { dst[e] = src[e]; src[e] = JT(0); }
+        }
+        if (lane < 2) {
+          double *rs = Rw + slot * 2 * max_tv + 2 * (u - vb) + lane;
+          if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + lane] = *rs;
+          *rs = 0.0;
+        }
+      }
+    };
+    flush(k, cur);
+    if (k == L - 1) flush(L, nxt);
+    wave_sync();
+
+#pragma unroll
+    for (int i = 0; i < NV; ++i) { zlo[i] += dz[i]; ulo[i] += du[i]; vlo[i] += dv[i]; }
   }
 }
 
@@ -326,17 +468,34 @@ __global__ void fill_zero_tail_kernel(uint32_t *__restrict__ p, int64_t n4) {
   if (i < n4) p[i] = 0u;
 }
 
-template <int NV, bool JAC, class JT>
+bool g_tables_ready[64] = {};
+
+fo_status ensure_tables(int device) {
+  if (device >= 0 && device < 64 && g_tables_ready[device]) return FO_OK;
+  static constexpr QTable tabs[2] = {make_table(3), make_table(4)};
+  FO_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(kQ), tabs, sizeof(tabs)));
+  if (device >= 0 && device < 64) g_tables_ready[device] = true;
+  return FO_OK;
+}
+
+template <int NV, bool JAC, class JT, bool N3>
 fo_status launch_t(const fo_mesh *mesh, const double *U, double *R, JT *J, int kind, hipStream_t s) {
   const MeshView &m = mesh->view;
-  const int64_t blocks = (m.n_cells + TEAMS_PER_BLOCK - 1) / TEAMS_PER_BLOCK;
-  if (blocks > 0x7fffffff) return fail(FO_EINVAL, "assembly: too many cells for one launch");
+  const size_t lds = (JAC ? 2 * size_t(mesh->max_slot) * sizeof(JT) : 0) +
+                     2 * 2 * size_t(mesh->max_task_verts) * sizeof(double);
   fo_status st = profile_begin(mesh, s);
   if (st != FO_OK) return st;
-  hipLaunchKernelGGL((assemble_kernel<NV, JAC, JT>), dim3(unsigned(blocks)), dim3(BLOCK), 0, s, m, U,
-                     R, J, kind == FO_JAC_PICARD ? 1 : 0);
-  FO_LAUNCH_CHECK("assemble_kernel");
+  hipLaunchKernelGGL((owner_kernel<NV, JAC, JT, N3>), dim3(unsigned(mesh->n_tasks)), dim3(WAVE), lds, s, m,
+                     mesh->tasks, U, R, J, kind == FO_JAC_PICARD ? 1 : 0, mesh->max_slot,
+                     mesh->max_task_verts);
+  FO_LAUNCH_CHECK("owner_kernel");
   return profile_end(mesh, s);
+}
+
+template <int NV, bool JAC, class JT>
+fo_status launch_n(const fo_mesh *mesh, const double *U, double *R, JT *J, int kind, hipStream_t s) {
+  if (mesh->view.n_glen == 3.0) return launch_t<NV, JAC, JT, true>(mesh, U, R, J, kind, s);
+  return launch_t<NV, JAC, JT, false>(mesh, U, R, J, kind, s);
 }
 
 }  // namespace
@@ -363,21 +522,19 @@ fo_status launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
 
 fo_status launch_assemble(const fo_mesh *mesh, const double *U, double *R, void *J, int dtype,
                           int kind, bool want_jac, hipStream_t s) {
-  const MeshView &m = mesh->view;
-  fo_status st;
-  if (R && (st = launch_fill_zero(R, sizeof(double) * m.n_dofs, s)) != FO_OK) return st;
+  fo_status st = ensure_tables(mesh->device);
+  if (st != FO_OK) return st;
+  const int nv = mesh->view.nv;
   if (!want_jac) {
-    if (m.nv == 3) return launch_t<3, false, double>(mesh, U, R, nullptr, kind, s);
-    return launch_t<4, false, double>(mesh, U, R, nullptr, kind, s);
+    if (nv == 3) return launch_n<3, false, double>(mesh, U, R, nullptr, kind, s);
+    return launch_n<4, false, double>(mesh, U, R, nullptr, kind, s);
   }
-  const size_t esz = dtype == FO_F32 ? 4 : 8;
-  if ((st = launch_fill_zero(J, esz * mesh->nnz, s)) != FO_OK) return st;
   if (dtype == FO_F32) {
-    if (m.nv == 3) return launch_t<3, true, float>(mesh, U, R, static_cast<float *>(J), kind, s);
-    return launch_t<4, true, float>(mesh, U, R, static_cast<float *>(J), kind, s);
+    if (nv == 3) return launch_n<3, true, float>(mesh, U, R, static_cast<float *>(J), kind, s);
+    return launch_n<4, true, float>(mesh, U, R, static_cast<float *>(J), kind, s);
   }
-  if (m.nv == 3) return launch_t<3, true, double>(mesh, U, R, static_cast<double *>(J), kind, s);
-  return launch_t<4, true, double>(mesh, U, R, static_cast<double *>(J), kind, s);
+  if (nv == 3) return launch_n<3, true, double>(mesh, U, R, static_cast<double *>(J), kind, s);
+  return launch_n<4, true, double>(mesh, U, R, static_cast<double *>(J), kind, s);
 }
 
 }  // namespace fo

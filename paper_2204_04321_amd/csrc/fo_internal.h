@@ -45,6 +45,13 @@ struct MeshView {
   const int32_t *cells;    // [T * nv]
   const uint8_t *rank;     // [T * nv * nv] rank[a][b]: position of vertex b in a's neighbour list
   const double *sigma;     // [L + 1]
+  // owner-computes work items: one per (vertex column v, base cell t containing v),
+  // ordered by v; item i covers cell vc_idx[i] where v sits at local corner vc_pos[i]
+  const int32_t *vc_ptr;   // [V + 1]
+  const int32_t *vc_idx;   // [T * nv]
+  const uint8_t *vc_pos;   // [T * nv]
+  const int32_t *item_vtx; // [T * nv] vertex of each item
+  const int32_t *slot_off; // [V] offset of v's rows inside its task's LDS level window
   double rho_g;            // rho * g
   double visc_pref;        // 1/2 A^(-1/n)
   double visc_exp;         // (1 - n) / (2 n)
@@ -72,6 +79,13 @@ struct fo_mesh {
   int32_t *self_rank = nullptr; // [V] position of each vertex in its own neighbour list
   int32_t *vc_ptr = nullptr;    // [V + 1] base cells around each vertex
   int32_t *vc_idx = nullptr;
+  uint8_t *vc_pos = nullptr;
+  int32_t *item_vtx = nullptr;
+  int32_t *slot_off = nullptr;
+  int4 *tasks = nullptr;        // [n_tasks] {member, v_begin, v_end, item_begin}
+  int32_t n_tasks = 0;
+  int32_t max_slot = 0;         // largest LDS level window (entries) over tasks
+  int32_t max_task_verts = 0;
   int64_t *rowptr = nullptr;    // [n_dofs + 1]
   int32_t *colidx = nullptr;    // [nnz]
   int device = 0;

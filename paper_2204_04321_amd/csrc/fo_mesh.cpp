@@ -69,7 +69,8 @@ static void free_mesh(fo_mesh *m) {
   if (!m) return;
   release_events(m);
   void *ptrs[] = {m->geo, m->sb, m->colptr, m->deg, m->cells, m->rank, m->sigma,
-                  m->nbr_ptr, m->nbr_idx, m->self_rank, m->vc_ptr, m->vc_idx, m->rowptr, m->colidx};
+                  m->nbr_ptr, m->nbr_idx, m->self_rank, m->vc_ptr, m->vc_idx, m->vc_pos,
+                  m->item_vtx, m->slot_off, m->tasks, m->rowptr, m->colidx};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -184,14 +185,48 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
         rank[(t * nv + a) * nv + b] = uint8_t(it - beg);
       }
     }
-  // vertex -> base cells (ordered by cell id), for vertex-gathered quantities
-  std::vector<int32_t> vc_ptr(V + 1, 0), vc_idx(size_t(T) * nv);
+  // vertex -> base cells (ordered by cell id): the owner-computes work items
+  std::vector<int32_t> vc_ptr(V + 1, 0), vc_idx(size_t(T) * nv), item_vtx(size_t(T) * nv);
+  std::vector<uint8_t> vc_pos(size_t(T) * nv);
   for (int64_t i = 0; i < T * nv; ++i) vc_ptr[C[i] + 1]++;
   for (int64_t v = 0; v < V; ++v) vc_ptr[v + 1] += vc_ptr[v];
   {
     std::vector<int32_t> fillp(vc_ptr.begin(), vc_ptr.end() - 1);
     for (int64_t t = 0; t < T; ++t)
-      for (int a = 0; a < nv; ++a) vc_idx[fillp[C[t * nv + a]]++] = int32_t(t);
+      for (int a = 0; a < nv; ++a) {
+        const int32_t v = C[t * nv + a];
+        const int32_t p = fillp[v]++;
+        vc_idx[p] = int32_t(t);
+        vc_pos[p] = uint8_t(a);
+        item_vtx[p] = v;
+      }
+  }
+  // wave tasks: runs of consecutive vertex columns with at most 64 items (one lane each)
+  // whose level windows (12 D entries per vertex) fit the per-wave LDS budget
+  constexpr int kMaxItems = 64, kMaxSlot = 2048;
+  std::vector<int4> tasks;
+  std::vector<int32_t> slot_off(V);
+  int32_t max_slot = 0, max_tv = 0;
+  {
+    int32_t vb = 0, items = 0, slot = 0;
+    for (int32_t v = 0; v < int32_t(V); ++v) {
+      const int32_t ni = vc_ptr[v + 1] - vc_ptr[v];
+      const int32_t sz = 12 * deg[v];
+      if (ni > kMaxItems || sz > kMaxSlot)
+        return fail(FO_EINVAL, "fo_mesh_create: vertex " + std::to_string(v) + " lies in more than 64 base cells");
+      if (v > vb && (items + ni > kMaxItems || slot + sz > kMaxSlot)) {
+        tasks.push_back(make_int4(0, vb, v, vc_ptr[vb]));
+        max_slot = std::max(max_slot, slot);
+        max_tv = std::max(max_tv, v - vb);
+        vb = v; items = 0; slot = 0;
+      }
+      slot_off[v] = slot;
+      items += ni;
+      slot += sz;
+    }
+    tasks.push_back(make_int4(0, vb, int32_t(V), vc_ptr[vb]));
+    max_slot = std::max(max_slot, slot);
+    max_tv = std::max(max_tv, int32_t(V) - vb);
   }
   std::vector<double4> geo(V);
   std::vector<double2> sb(V);
@@ -218,6 +253,10 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   UP(self_rank, self_rank);
   UP(vc_ptr, vc_ptr);
   UP(vc_idx, vc_idx);
+  UP(vc_pos, vc_pos);
+  UP(item_vtx, item_vtx);
+  UP(slot_off, slot_off);
+  UP(tasks, tasks);
 #undef UP
   if ((st = dev_upload(&m->cells, C, size_t(T) * nv, s)) != FO_OK) { free_mesh(m); return st; }
   if ((st = dev_upload<int64_t>(&m->rowptr, nullptr, size_t(n_dofs + 1), s)) != FO_OK) { free_mesh(m); return st; }
@@ -237,6 +276,14 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   mv.cells = m->cells;
   mv.rank = m->rank;
   mv.sigma = m->sigma;
+  mv.vc_ptr = m->vc_ptr;
+  mv.vc_idx = m->vc_idx;
+  mv.vc_pos = m->vc_pos;
+  mv.item_vtx = m->item_vtx;
+  mv.slot_off = m->slot_off;
+  m->n_tasks = int32_t(tasks.size());
+  m->max_slot = max_slot;
+  m->max_task_verts = max_tv;
   mv.rho_g = d->rho * d->g;
   mv.visc_pref = 0.5 * std::pow(d->A, -1.0 / d->n);
   mv.visc_exp = (1.0 - d->n) / (2.0 * d->n);
