@@ -175,7 +175,7 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
   const int slot_size = m.slot_off[ve - 1] + 12 * m.deg[ve - 1];
 
   // ---- per-item constants -----------------------------------------------------------------
-  int vid[NV], rk[NV];
+  int vid[NV];
   double xl[NV], yl[NV], bed[NV], Hh[NV], su[NV];
   // horizontal coordinates relative to the cell's first corner, the bed, H and s
   auto load_geo = [&](double *xl_, double *yl_, double *bed_, double *H_, double *s_) {
@@ -192,10 +192,7 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
     }
   };
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    vid[i] = m.cells[int64_t(t) * NV + i];
-    rk[i] = m.rank[(int64_t(t) * NV + al) * NV + i];
-  }
+  for (int i = 0; i < NV; ++i) vid[i] = m.cells[int64_t(t) * NV + i];
   load_geo(xl, yl, bed, Hh, su);
   // P1 triangles: the horizontal basis gradients and the map determinant are constant
   double lxc[NV], lyc[NV], detc = 0, sxc = 0, syc = 0;
@@ -221,30 +218,39 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
   }
   for (int e = lane; e < 2 * (ve - vb); e += WAVE) { Rw[e] = 0.0; Rw[2 * max_tv + e] = 0.0; }
 
-  // level-k nodal data of the cell's vertices (carried up the column)
-  double zlo[NV], ulo[NV], vlo[NV];
-  {
-    const double s0 = m.sigma[0];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      zlo[i] = bed[i] + s0 * Hh[i];
-      const double2 uv = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1)));
-      ulo[i] = uv.x; vlo[i] = uv.y;
-    }
-  }
   wave_sync();
 
   for (int k = 0; k < L; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
-    // gather level k+1 as increments over level k
-    double dz[NV], du[NV], dv[NV];
-    const double s1 = m.sigma[k + 1];
+    // gather levels k and k+1 (repeat loads hit the cache; nothing is carried between
+    // layers so the quadrature loop keeps few registers live)
+    double zlo[NV], ulo[NV], vlo[NV], dz[NV], du[NV], dv[NV];
+    const double s0 = m.sigma[k], s1 = m.sigma[k + 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      dz[i] = (bed[i] + s1 * Hh[i]) - zlo[i];
-      const double2 uv = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1) + k + 1));
-      du[i] = uv.x - ulo[i];
-      dv[i] = uv.y - vlo[i];
+      const double4 g = m.geo[vid[i]];
+      zlo[i] = g.z + s0 * g.w;
+      dz[i] = (g.z + s1 * g.w) - zlo[i];
+      const double2 a0 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1) + k));
+      const double2 a1 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1) + k + 1));
+      ulo[i] = a0.x; vlo[i] = a0.y;
+      du[i] = a1.x - a0.x;
+      dv[i] = a1.y - a0.y;
+    }
+    // wedges: x/y slopes of z, u, v at fixed zeta are (level-k sum) + zeta (increment sum)
+    double HS[12];
+    if constexpr (NV == 3) {
+#pragma unroll
+      for (int h = 0; h < 12; ++h) HS[h] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        HS[0] = fma(lxc[i], zlo[i], HS[0]); HS[1] = fma(lxc[i], dz[i], HS[1]);
+        HS[2] = fma(lyc[i], zlo[i], HS[2]); HS[3] = fma(lyc[i], dz[i], HS[3]);
+        HS[4] = fma(lxc[i], ulo[i], HS[4]); HS[5] = fma(lxc[i], du[i], HS[5]);
+        HS[6] = fma(lyc[i], ulo[i], HS[6]); HS[7] = fma(lyc[i], du[i], HS[7]);
+        HS[8] = fma(lxc[i], vlo[i], HS[8]); HS[9] = fma(lxc[i], dv[i], HS[9]);
+        HS[10] = fma(lyc[i], vlo[i], HS[10]); HS[11] = fma(lyc[i], dv[i], HS[11]);
+      }
     }
 
     // residual rows of v's lower (index 0) and upper (index 1) node, and their tangents:
@@ -293,18 +299,28 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
         }
       }
       // vertical map: z_zeta and the slopes of z along x, y at fixed zeta
-      double zze = 0, zxs = 0, zys = 0;
-      double ucx = 0, ucy = 0, vcx = 0, vcy = 0, dum = 0, dvm = 0;
+      double zze = 0, zxs, zys, ucx, ucy, vcx, vcy, dum = 0, dvm = 0;
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
-        const double zc = zlo[i] + zeta * dz[i];
-        const double uc = ulo[i] + zeta * du[i];
-        const double vc = vlo[i] + zeta * dv[i];
-        zze += lam[i] * dz[i];
-        zxs += lx[i] * zc; zys += ly[i] * zc;
-        ucx += lx[i] * uc; ucy += ly[i] * uc;
-        vcx += lx[i] * vc; vcy += ly[i] * vc;
-        dum += lam[i] * du[i]; dvm += lam[i] * dv[i];
+        zze = fma(lam[i], dz[i], zze);
+        dum = fma(lam[i], du[i], dum);
+        dvm = fma(lam[i], dv[i], dvm);
+      }
+      if constexpr (NV == 3) {
+        zxs = fma(zeta, HS[1], HS[0]); zys = fma(zeta, HS[3], HS[2]);
+        ucx = fma(zeta, HS[5], HS[4]); ucy = fma(zeta, HS[7], HS[6]);
+        vcx = fma(zeta, HS[9], HS[8]); vcy = fma(zeta, HS[11], HS[10]);
+      } else {
+        zxs = zys = ucx = ucy = vcx = vcy = 0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          const double zc = fma(zeta, dz[i], zlo[i]);
+          const double uc = fma(zeta, du[i], ulo[i]);
+          const double vc = fma(zeta, dv[i], vlo[i]);
+          zxs = fma(lx[i], zc, zxs); zys = fma(ly[i], zc, zys);
+          ucx = fma(lx[i], uc, ucx); ucy = fma(ly[i], uc, ucy);
+          vcx = fma(lx[i], vc, vcx); vcy = fma(ly[i], vc, vcy);
+        }
       }
       const double iz = rcp64(zze);
       const double px = -zxs * iz, py = -zys * iz;        // d zeta / dx, d zeta / dy
@@ -332,41 +348,49 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
       const double atx = l1 * lxa + lam_a * px, aty = l1 * lya + lam_a * py, atz = lam_a * iz;
       const double gb0 = e1x * abx + e1y * aby + e1z * abz, gb1 = e2x * abx + e2y * aby + e2z * abz;
       const double gt0 = e1x * atx + e1y * aty + e1z * atz, gt1 = e2x * atx + e2y * aty + e2z * atz;
-      Rb0 += s2 * gb0 + gvx * (lam_a * l0);
-      Rb1 += s2 * gb1 + gvy * (lam_a * l0);
-      Rt0 += s2 * gt0 + gvx * (lam_a * l1);
-      Rt1 += s2 * gt1 + gvy * (lam_a * l1);
+      const double nb = lam_a * l0, nt = lam_a * l1;     // v's basis functions at q
+      Rb0 = fma(s2, gb0, fma(gvx, nb, Rb0));
+      Rb1 = fma(s2, gb1, fma(gvy, nb, Rb1));
+      Rt0 = fma(s2, gt0, fma(gvx, nt, Rt0));
+      Rt1 = fma(s2, gt1, fma(gvy, nt, Rt1));
       if constexpr (JAC) {
         // row side: 2 mu W times the row node's gradient (with the constant factors of
         // d(eps_c . grad N_a)/dU), and 2 mu' W times its strain projection
         AT RX[2][9];
         {
-          const double ax[2] = {abx, atx}, ay[2] = {aby, aty}, az[2] = {abz, atz};
-          const double g0[2] = {gb0, gt0}, g1[2] = {gb1, gt1};
+          const AT s2a = AT(s2), t2a = AT(t2);
+          const AT ax[2] = {AT(abx), AT(atx)}, ay[2] = {AT(aby), AT(aty)}, az[2] = {AT(abz), AT(atz)};
+          const AT g0[2] = {AT(gb0), AT(gt0)}, g1[2] = {AT(gb1), AT(gt1)};
 #pragma unroll
           for (int a = 0; a < 2; ++a) {
-            const double Ax = s2 * ax[a], Ay = s2 * ay[a], Az = s2 * az[a];
-            RX[a][0] = AT(2.0 * Ax); RX[a][1] = AT(0.5 * Ay); RX[a][2] = AT(0.5 * Az);
-            RX[a][3] = AT(Ax);       RX[a][4] = AT(Ay);       RX[a][5] = AT(0.5 * Ax);
-            RX[a][6] = AT(2.0 * Ay); RX[a][7] = AT(t2 * g0[a]); RX[a][8] = AT(t2 * g1[a]);
+            const AT Ax = s2a * ax[a], Ay = s2a * ay[a], Az = s2a * az[a];
+            RX[a][0] = Ax + Ax;        RX[a][1] = AT(0.5) * Ay; RX[a][2] = AT(0.5) * Az;
+            RX[a][3] = Ax;             RX[a][4] = Ay;           RX[a][5] = AT(0.5) * Ax;
+            RX[a][6] = Ay + Ay;        RX[a][7] = t2a * g0[a];  RX[a][8] = t2a * g1[a];
           }
         }
+        // column side in the derivative type: d(grad N_b) and d(eps_e^2) along (b, u|v)
+        const AT pxa = AT(px), pya = AT(py), iza = AT(iz);
+        const AT e1xa = AT(e1x), e1ya = AT(e1y), e1za = AT(e1z);
+        const AT e2xa = AT(e2x), e2ya = AT(e2y), e2za = AT(e2z);
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
+          const AT lxj = AT(lx[j]), lyj = AT(ly[j]), lmj = AT(lam[j]);
 #pragma unroll
           for (int lev = 0; lev < 2; ++lev) {
-            const double ll = lev ? l1 : l0;
-            const double dl = lev ? lam[j] : -lam[j];
-            const double bxd = ll * lx[j] + dl * px, byd = ll * ly[j] + dl * py, bzd = dl * iz;
-            const AT bx = AT(bxd), by = AT(byd), bz = AT(bzd);
-            const AT gu = AT(e1x * bxd + e1y * byd + e1z * bzd);   // d(eps_e^2)/dU_(b,u)
-            const AT gv = AT(e2x * bxd + e2y * byd + e2z * bzd);   // d(eps_e^2)/dU_(b,v)
+            const AT ll = AT(lev ? l1 : l0);
+            const AT dl = lev ? lmj : -lmj;
+            const AT bx = fma(ll, lxj, dl * pxa), by = fma(ll, lyj, dl * pya), bz = dl * iza;
+            const AT gu = fma(e1xa, bx, fma(e1ya, by, e1za * bz));   // d(eps_e^2)/dU_(b,u)
+            const AT gv = fma(e2xa, bx, fma(e2ya, by, e2za * bz));   // d(eps_e^2)/dU_(b,v)
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-              Jx[a][0][0][j][lev] += RX[a][0] * bx + RX[a][1] * by + RX[a][2] * bz + RX[a][7] * gu;
-              Jx[a][0][1][j][lev] += RX[a][3] * by + RX[a][1] * bx + RX[a][7] * gv;
-              Jx[a][1][0][j][lev] += RX[a][4] * bx + RX[a][5] * by + RX[a][8] * gu;
-              Jx[a][1][1][j][lev] += RX[a][5] * bx + RX[a][6] * by + RX[a][2] * bz + RX[a][8] * gv;
+              AT &uu = Jx[a][0][0][j][lev], &uv = Jx[a][0][1][j][lev];
+              AT &vu = Jx[a][1][0][j][lev], &vv = Jx[a][1][1][j][lev];
+              uu = fma(RX[a][0], bx, uu); uu = fma(RX[a][1], by, uu); uu = fma(RX[a][2], bz, uu); uu = fma(RX[a][7], gu, uu);
+              uv = fma(RX[a][3], by, uv); uv = fma(RX[a][1], bx, uv); uv = fma(RX[a][7], gv, uv);
+              vu = fma(RX[a][4], bx, vu); vu = fma(RX[a][5], by, vu); vu = fma(RX[a][8], gu, vu);
+              vv = fma(RX[a][5], bx, vv); vv = fma(RX[a][6], by, vv); vv = fma(RX[a][2], bz, vv); vv = fma(RX[a][8], gv, vv);
             }
           }
         }
@@ -413,6 +437,9 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
       lds_add(Rnxt + rloc, Rt0);
       lds_add(Rnxt + rloc + 1, Rt1);
       if constexpr (JAC) {
+        int rk[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) rk[i] = m.rank[(int64_t(t) * NV + al) * NV + i];
         const int nlk = nlev(k, L), nl1 = nlev(k + 1, L);
         const int offk = k > 0 ? 1 : 0;     // level k sits at window position 1 unless k = 0
         JT *Wk = Jw + cur * max_slot + soff, *Wk1 = Jw + nxt * max_slot + soff;
@@ -432,19 +459,46 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
     wave_sync();
 
     // ---- level k is complete: copy it to its CSR rows and clear it for level k+2 ------------
+    // Copy out four vertex columns at a time: all LDS reads of a batch are issued before
+    // the first global store, so one LDS latency is exposed per batch, not per chunk.
     auto flush = [&](int lev_k, int slot) {
-      for (int u = vb; u < ve; ++u) {
-        const int Du = m.deg[u];
+      const int nl = nlev(lev_k, L);
+      for (int u0 = vb; u0 < ve; u0 += 4) {
         if constexpr (JAC) {
-          const int n = 4 * nlev(lev_k, L) * Du;
-          JT *src = Jw + slot * max_slot + m.slot_off[u];
-          JT *dst = J + m.colptr[u] + int64_t(4) * Du * cumlev(lev_k);
-          for (int e = lane; e < n; e += WAVE) { dst[e] = src[e]; src[e] = JT(0); }
+          JT val[4][3];
+          int nn[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int u = u0 + i;
+            nn[i] = u < ve ? 4 * nl * m.deg[u] : 0;
+            const JT *src = Jw + slot * max_slot + (u < ve ? m.slot_off[u] : 0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const int e = lane + c * WAVE;
+              val[i][c] = e < nn[i] ? src[e] : JT(0);
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int u = u0 + i;
+            if (u >= ve) break;
+            JT *src = Jw + slot * max_slot + m.slot_off[u];
+            JT *dst = J + m.colptr[u] + int64_t(4) * m.deg[u] * cumlev(lev_k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const int e = lane + c * WAVE;
+              if (e < nn[i]) { dst[e] = val[i][c]; src[e] = JT(0); }
+            }
+            for (int e = lane + 3 * WAVE; e < nn[i]; e += WAVE) { dst[e] = src[e]; src[e] = JT(0); }
+          }
         }
-        if (lane < 2) {
-          double *rs = Rw + slot * 2 * max_tv + 2 * (u - vb) + lane;
-          if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + lane] = *rs;
-          *rs = 0.0;
+        if (lane < 8) {
+          const int u = u0 + (lane >> 1);
+          if (u < ve) {
+            double *rs = Rw + slot * 2 * max_tv + 2 * (u - vb) + (lane & 1);
+            if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + (lane & 1)] = *rs;
+            *rs = 0.0;
+          }
         }
       }
     };
@@ -452,8 +506,6 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
     if (k == L - 1) flush(L, nxt);
     wave_sync();
 
-#pragma unroll
-    for (int i = 0; i < NV; ++i) { zlo[i] += dz[i]; ulo[i] += du[i]; vlo[i] += dv[i]; }
   }
 }
 
