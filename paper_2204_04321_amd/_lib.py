@@ -34,6 +34,32 @@ class MeshDesc(C.Structure):
     ]
 
 
+class NewtonOpts(C.Structure):
+    _fields_ = [
+        ("tol", C.c_double), ("max_newton", C.c_int32), ("lin_rtol", C.c_double),
+        ("gmres_restart", C.c_int32), ("max_lin", C.c_int32), ("jac_dtype", C.c_int32),
+        ("max_backtracks", C.c_int32), ("init", C.c_int32),
+    ]
+
+
+class NewtonReport(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("newton_its", C.c_int32), ("lin_its", C.c_int64),
+        ("residual_calls", C.c_int32), ("jacobian_calls", C.c_int32), ("backtracks", C.c_int32),
+        ("f0_norm", C.c_double), ("final_norm", C.c_double), ("final_rel", C.c_double),
+        ("ms_total_fill", C.c_double), ("ms_prec_construction", C.c_double),
+        ("ms_linear_solve", C.c_double), ("ms_total_solve", C.c_double),
+        ("res_hist", C.c_double * 64),
+    ]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "res_hist"}
+        d["res_hist"] = [self.res_hist[i] for i in range(min(64, self.newton_its + 1))]
+        return d
+
+
+FO_INIT_USER, FO_INIT_SIA = 0, 1
+
 _lib = None
 
 
@@ -49,6 +75,10 @@ def _declare(lib):
         "fo_initial_guess_sia": (C.c_int, [vp, vp, vp]),
         "fo_profile_enable": (C.c_int, [vp, i32]),
         "fo_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), i64p]),
+        "fo_newton_default_opts": (None, [C.POINTER(NewtonOpts)]),
+        "fo_newton_workspace_bytes": (C.c_size_t, [vp, C.POINTER(NewtonOpts)]),
+        "fo_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport), vp,
+                                      C.c_size_t, vp]),
         "fo_status_string": (C.c_char_p, [C.c_int]),
         "fo_last_error": (C.c_char_p, []),
     }

@@ -113,6 +113,44 @@ class Mesh:
         check(_lib.lib().fo_initial_guess_sia(self.handle, _ptr(U), _stream(stream)))
         return U
 
+    # ---- Newton solve ---------------------------------------------------------------------
+    def newton_opts(self, **kw) -> "_lib.NewtonOpts":
+        o = _lib.NewtonOpts()
+        _lib.lib().fo_newton_default_opts(C.byref(o))
+        for k, v in kw.items():
+            if k == "jac_dtype":
+                v = FO_F64 if v in ("f64", FO_F64) else FO_F32
+            elif k == "init":
+                v = {"user": _lib.FO_INIT_USER, "sia": _lib.FO_INIT_SIA}.get(v, v)
+            setattr(o, k, v)
+        return o
+
+    def workspace_bytes(self, opts) -> int:
+        n = _lib.lib().fo_newton_workspace_bytes(self.handle, C.byref(opts))
+        if n == 0:
+            raise ValueError("bad Newton options")
+        return int(n)
+
+    def newton_solve(self, U: torch.Tensor, workspace: torch.Tensor | None = None,
+                     check_status: bool = False, stream=None, **kw) -> dict:
+        """Damped Newton in place on U (device float64 [n_dofs]).  Returns the report as a
+        dict; status != 0 (not converged, non-finite) is reported, raised only if
+        check_status."""
+        self._check_vec(U)
+        opts = self.newton_opts(**kw)
+        need = self.workspace_bytes(opts)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        rep = _lib.NewtonReport()
+        st = _lib.lib().fo_newton_solve(self.handle, _ptr(U), C.byref(opts), C.byref(rep),
+                                        _ptr(workspace), workspace.numel(), _stream(stream))
+        d = rep.as_dict()
+        d["status"] = st
+        d["message"] = _lib.lib().fo_last_error().decode() if st != 0 else ""
+        if check_status:
+            check(st)
+        return d
+
     # ---- measurement ----------------------------------------------------------------------
     def profile(self, on: bool = True):
         check(_lib.lib().fo_profile_enable(self.handle, 1 if on else 0))

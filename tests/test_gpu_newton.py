@@ -1,0 +1,85 @@
+"""GPU damped Newton (GMRES + vertical-column block preconditioner) against the oracle's
+direct-solve Newton, and its failure paths (forced from the host)."""
+import numpy as np
+import pytest
+import torch
+
+from fo_inputs import config0_slab
+from fo_inputs.meshgen import ExtrudedMesh, _dome_fields, dome_velocity, ellipse_mesh
+from oracle import fo_oracle as fo
+from oracle import solve
+
+from gpu_util import gpu_mesh, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _cap(seed=11, n_points=400, L=6):
+    rng = np.random.default_rng(seed)
+    a, b = 70e3, 40e3
+    xy, tri = ellipse_mesh(n_points, a, b, rng)
+    s, H, beta = _dome_fields(xy, a, b, rng, 2000.0, 300.0, 500.0, 1.0, 15e3, 60e3)
+    return ExtrudedMesh("wedge", xy, tri, s, H, beta, np.linspace(0, 1, L + 1), A=1e-16)
+
+
+@pytest.fixture(scope="module")
+def cap():
+    m = _cap()
+    U_ref, info = solve.newton_solve(m, solve.sia_guess(m), tol=1e-11)
+    assert info["status"] == "converged"
+    return m, U_ref, gpu_mesh(m)
+
+
+@pytest.mark.parametrize("jdt", ["f64", "f32"])
+def test_newton_matches_oracle_solution(cap, jdt):
+    m, U_ref, M = cap
+    U = to_dev(solve.sia_guess(m))
+    rep = M.newton_solve(U, tol=1e-8, jac_dtype=jdt)
+    print(f"\n[newton {jdt}] its {rep['newton_its']} gmres {rep['lin_its']} "
+          f"res {rep['final_rel']:.2e} fill {rep['ms_total_fill']:.1f} ms lin {rep['ms_linear_solve']:.1f} ms")
+    assert rep["status"] == 0, rep
+    assert rep["final_rel"] <= 1e-8
+    Ug = U.cpu().numpy()
+    # the residual the GPU reached, recomputed by the oracle
+    f0 = np.linalg.norm(fo.residual(m, np.zeros_like(Ug)))
+    assert np.linalg.norm(fo.residual(m, Ug)) <= 1.01e-8 * f0
+    assert np.abs(Ug - U_ref).max() <= 1e-5 * np.abs(U_ref).max()
+
+
+def test_newton_sia_init_and_slab():
+    m, U0 = config0_slab()
+    M = gpu_mesh(m)
+    U = torch.zeros(M.n_dofs, dtype=torch.float64, device="cuda")
+    rep = M.newton_solve(U, tol=1e-8, init="sia")
+    assert rep["status"] == 0, rep
+    Ug = U.cpu().numpy()
+    f0 = np.linalg.norm(fo.residual(m, np.zeros_like(Ug)))
+    assert np.linalg.norm(fo.residual(m, Ug)) <= 1.01e-8 * f0
+    # the paper's regression check: mean of the final solution (Sec. 3.4 style) vs the oracle
+    U_ref, info = solve.newton_solve(m, solve.sia_guess(m), tol=1e-10)
+    assert abs(Ug.mean() - U_ref.mean()) <= 1e-5 * abs(U_ref.mean())
+
+
+def test_newton_iteration_cap_reports_not_converged(cap):
+    m, _, M = cap
+    U = to_dev(solve.sia_guess(m))
+    rep = M.newton_solve(U, tol=1e-12, max_newton=1)
+    assert rep["status"] == -6 and rep["newton_its"] == 1
+    assert "cap" in rep["message"]
+
+
+def test_newton_nonfinite_guess_is_reported(cap):
+    m, _, M = cap
+    U0 = solve.sia_guess(m)
+    U0[7] = np.nan
+    U = to_dev(U0)
+    rep = M.newton_solve(U, tol=1e-8)
+    assert rep["status"] == -5
+
+
+def test_newton_rejects_bad_options(cap):
+    from paper_2204_04321_amd import FoError
+    m, _, M = cap
+    U = to_dev(solve.sia_guess(m))
+    with pytest.raises(ValueError):
+        M.newton_solve(U, gmres_restart=0)
