@@ -187,13 +187,16 @@ def viscosity(q, A, n, eps0):
 
 def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | None = None,
                    want_jac: bool = True, picard: bool = False, xyz=None, hooks=None,
-                   s_drive=None):
+                   s_drive=None, absolute: bool = False):
     """Element residuals [nc, npe, 2] and (optionally) element Jacobians
     [nc, npe, 2, npe, 2] for the given cells.
 
     U may be complex (complex-step differentiation of the residual).  s_drive is a
     test-only override of the per-vertex surface used in the driving-stress term
-    (the geometry always comes from the mesh's own s and H)."""
+    (the geometry always comes from the mesh's own s and H).  absolute=True returns,
+    instead of the sums, the sums of the absolute values of every quadrature-point
+    term (the scale of the rounding error of any summation order)."""
+    ab = np.abs if absolute else (lambda x: x)
     ref = ref or RefElement(mesh.elem)
     xyz = node_xyz(mesh) if xyz is None else xyz
     nodes = cell_nodes(mesh)[cell_ids]
@@ -216,7 +219,8 @@ def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | 
     sx = np.einsum("ca,cqa->cq", s_nodes, gradN[..., 0])
     sy = np.einsum("ca,cqa->cq", s_nodes, gradN[..., 1])
     grav = np.stack([sx, sy], axis=-1)                       # [nc, nq, 2]
-    Re = np.einsum("eq,eqak->eak", W * 2 * mu, g) + rg * np.einsum("eq,qa,eqk->eak", W, ref.N, grav)
+    Re = (np.einsum("eqak->eak", ab(np.einsum("eq,eqak->eqak", W * 2 * mu, g)))
+          + rg * np.einsum("eqak->eak", ab(np.einsum("eq,qa,eqk->eqak", W, ref.N, grav))))
     Je = None
     if want_jac:
         gx, gy, gz = gradN[..., 0], gradN[..., 1], gradN[..., 2]
@@ -230,9 +234,14 @@ def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | 
         # K[e, q, a, k, b, l]: row dof (a, k), column dof (b, l)
         K = np.stack([np.stack([Kuu, Kuv], axis=-1), np.stack([Kvu, Kvv], axis=-1)], axis=-2)
         K = K.transpose(0, 1, 2, 4, 3, 5)
-        Je = np.einsum("eq,eqakbl->eakbl", W * 2 * mu, K)
-        if not picard:
-            Je = Je + np.einsum("eq,eqak,eqbl->eakbl", W * 2 * dmu, g, g)
+        if absolute:
+            Je = np.einsum("eq,eqakbl->eakbl", np.abs(W * 2 * mu), np.abs(K))
+            if not picard:
+                Je = Je + np.einsum("eq,eqak,eqbl->eakbl", np.abs(W * 2 * dmu), np.abs(g), np.abs(g))
+        else:
+            Je = np.einsum("eq,eqakbl->eakbl", W * 2 * mu, K)
+            if not picard:
+                Je = Je + np.einsum("eq,eqak,eqbl->eakbl", W * 2 * dmu, g, g)
     # bed friction on the lower face of the bottom layer
     L = mesh.n_layers
     bottom = (cell_ids % L) == 0
@@ -245,9 +254,9 @@ def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | 
         beta_nodes = node_column_field(mesh, mesh.beta)[nodes[bidx]]
         beta_r = np.einsum("ca,ra->cr", beta_nodes, ref.Nb)
         ur = np.einsum("eak,ra->erk", Ue[bidx], ref.Nb)
-        Re[bidx] += np.einsum("er,erk,ra->eak", dA * beta_r, ur, ref.Nb)
+        Re[bidx] += np.einsum("erak->eak", ab(np.einsum("er,erk,ra->erak", dA * beta_r, ur, ref.Nb)))
         if want_jac:
-            M = np.einsum("er,ra,rb->eab", dA * beta_r, ref.Nb, ref.Nb)
+            M = np.einsum("erab->eab", ab(np.einsum("er,ra,rb->erab", dA * beta_r, ref.Nb, ref.Nb)))
             Je[bidx, :, 0, :, 0] += M
             Je[bidx, :, 1, :, 1] += M
     if hooks is not None:
@@ -296,8 +305,11 @@ def residual(mesh, U, **kw):
 
 
 def abs_scales(mesh, U, picard=False, chunk=20000, cells=None):
-    """Row scales sum_e |R_e,i| and max_j sum_e |J_e,ij| used to judge rounding-level parity
-    (optionally from a subset of cells: exact for rows whose cells are all included)."""
+    """Row scales for rounding-level parity: sum over cells and quadrature points of the
+    absolute values of the terms summed into R_i, and max_j of the same for J_ij (optionally
+    from a subset of cells: exact for rows whose cells are all included).  Any summation
+    order of the same terms differs from another by at most a small multiple of the unit
+    roundoff times these sums."""
     ref = RefElement(mesh.elem)
     xyz = node_xyz(mesh)
     nd = mesh.n_dofs
@@ -306,7 +318,7 @@ def abs_scales(mesh, U, picard=False, chunk=20000, cells=None):
     all_cells = np.arange(mesh.n_cells) if cells is None else np.asarray(cells)
     for ch in _chunks(all_cells.shape[0], chunk):
         ids = all_cells[ch]
-        Re, Je, nodes = element_arrays(mesh, ids, U, ref, True, picard, xyz)
+        Re, Je, nodes = element_arrays(mesh, ids, U, ref, True, picard, xyz, absolute=True)
         dofs = (2 * nodes[:, :, None] + np.arange(2)[None, None, :]).reshape(ids.shape[0], -1)
         rs += np.bincount(dofs.ravel(), weights=np.abs(Re).reshape(-1), minlength=nd)
         m = dofs.shape[1]
