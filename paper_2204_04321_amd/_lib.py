@@ -79,6 +79,9 @@ def _declare(lib):
         "fo_newton_workspace_bytes": (C.c_size_t, [vp, C.POINTER(NewtonOpts)]),
         "fo_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport), vp,
                                       C.c_size_t, vp]),
+        "fo_ensemble_create": (C.c_int, [C.POINTER(vp), i32, vp, C.POINTER(vp)]),
+        "fo_ensemble_destroy": (None, [vp]),
+        "fo_ensemble_assemble": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i32, i32, vp]),
         "fo_status_string": (C.c_char_p, [C.c_int]),
         "fo_last_error": (C.c_char_p, []),
     }

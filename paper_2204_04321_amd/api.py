@@ -164,3 +164,39 @@ class Mesh:
     def _check_vec(self, U):
         if U.dtype != torch.float64 or U.numel() != self.n_dofs:
             raise ValueError(f"expected float64 vector of {self.n_dofs} dofs")
+
+
+class Ensemble:
+    """Several uploaded meshes (same element type) assembled by one persistent launch."""
+
+    def __init__(self, meshes, stream=None):
+        self.meshes = list(meshes)
+        arr = (C.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        h = C.c_void_p()
+        check(_lib.lib().fo_ensemble_create(arr, len(self.meshes), _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lib().fo_ensemble_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def assemble(self, Us, Rs=None, Js=None, dtype: str = "f64", kind: str = "newton", stream=None):
+        """Us: list of device float64 vectors; Rs: list (or None); Js: list of value
+        buffers (or None for residuals only).  Buffers are written in place."""
+        n = len(self.meshes)
+        for M, U in zip(self.meshes, Us):
+            M._check_vec(U)
+        P = C.c_void_p * n
+        u = P(*[_ptr(U) for U in Us])
+        r = P(*[(_ptr(R) if R is not None else None) for R in Rs]) if Rs is not None else None
+        j = P(*[_ptr(J) for J in Js]) if Js is not None else None
+        check(_lib.lib().fo_ensemble_assemble(
+            self.handle, u, r, j, FO_F64 if dtype == "f64" else FO_F32,
+            FO_JAC_NEWTON if kind == "newton" else FO_JAC_PICARD, _stream(stream)))

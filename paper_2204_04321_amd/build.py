@@ -22,6 +22,7 @@ SOURCES = [
     "fo_assemble.hip",
     "fo_solver.hip",
     "fo_newton.cpp",
+    "fo_ensemble.cpp",
 ]
 
 ARCH = "gfx950"

@@ -148,19 +148,16 @@ __device__ __forceinline__ T sel4(int i, T a, T b, T c, T d) {
 // N3 selects the n = 3 viscosity power; JAC adds the Jacobian; JT is its value type
 // (double, or float with FP32 derivative arithmetic over the FP64 primal).
 template <int NV, bool JAC, class JT, bool N3>
-__global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__restrict__ tasks,
-                                                     const double *__restrict__ U, double *__restrict__ R,
-                                                     JT *__restrict__ J, int picard, int max_slot,
-                                                     int max_tv) {
+__device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, const double *__restrict__ U,
+                                           double *__restrict__ R, JT *__restrict__ J, int picard,
+                                           int max_slot, int max_tv, unsigned char *smem) {
   constexpr int NQ = Elem<NV>::NQ, NQB = Elem<NV>::NQB;
   using AT = JT;   // derivative arithmetic type
   const QTable &Q = kQ[NV == 3 ? 0 : 1];
-  extern __shared__ __align__(16) unsigned char smem[];
   JT *Jw = reinterpret_cast<JT *>(smem);                                                     // [2][max_slot]
   double *Rw = reinterpret_cast<double *>(smem + (JAC ? 2 * size_t(max_slot) * sizeof(JT) : 0));  // [2][2 max_tv]
 
   const int lane = threadIdx.x;
-  const int4 task = tasks[blockIdx.x];
   const int vb = task.y, ve = task.z, ib = task.w;
   const int ie = m.vc_ptr[ve];
   const bool act = ib + lane < ie;
@@ -509,6 +506,36 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
   }
 }
 
+template <int NV, bool JAC, class JT, bool N3>
+__global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__restrict__ tasks,
+                                                     const double *__restrict__ U, double *__restrict__ R,
+                                                     JT *__restrict__ J, int picard, int max_slot,
+                                                     int max_tv) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  owner_task<NV, JAC, JT, N3>(m, tasks[blockIdx.x], U, R, J, picard, max_slot, max_tv, smem);
+}
+
+// Persistent ensemble launch: each workgroup repeatedly takes the next (member, task) pair
+// from a device counter until the combined task table is exhausted (every wave exits).
+template <int NV, bool JAC, class JT, bool N3>
+__global__ __launch_bounds__(WAVE) void ensemble_kernel(const EnsembleMember *__restrict__ mem,
+                                                        const int4 *__restrict__ tasks, int n_tasks,
+                                                        int *__restrict__ counter, int picard) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int ti = next;
+    __syncthreads();
+    if (ti >= n_tasks) break;
+    const int4 task = tasks[ti];
+    const EnsembleMember &e = mem[task.x];
+    owner_task<NV, JAC, JT, N3>(e.view, task, e.U, e.R, static_cast<JT *>(e.J), picard, e.max_slot,
+                                e.max_tv, smem);
+  }
+}
+
 __global__ void fill_zero_kernel(uint4 *__restrict__ p, int64_t n16) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
@@ -550,7 +577,46 @@ fo_status launch_n(const fo_mesh *mesh, const double *U, double *R, JT *J, int k
   return launch_t<NV, JAC, JT, false>(mesh, U, R, J, kind, s);
 }
 
+template <int NV, bool JAC, class JT, bool N3>
+fo_status launch_ens_t(const EnsembleLaunch &E, int kind, hipStream_t s) {
+  const size_t lds = (JAC ? 2 * size_t(E.max_slot) * sizeof(JT) : 0) + 2 * 2 * size_t(E.max_tv) * sizeof(double);
+  auto kern = ensemble_kernel<NV, JAC, JT, N3>;
+  int per_cu = 0;
+  FO_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVE, lds));
+  if (per_cu < 1) per_cu = 1;
+  int64_t grid = int64_t(E.n_cu) * per_cu;
+  if (grid > E.n_tasks) grid = E.n_tasks;
+  if (grid < 1) grid = 1;
+  fo_status st = launch_fill_zero(E.counter, 16, s);
+  if (st != FO_OK) return st;
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(WAVE), lds, s, E.members, E.tasks, E.n_tasks, E.counter,
+                     kind == FO_JAC_PICARD ? 1 : 0);
+  FO_LAUNCH_CHECK("ensemble_kernel");
+  return FO_OK;
+}
+
+template <int NV, bool JAC, class JT>
+fo_status launch_ens_n(const EnsembleLaunch &E, int kind, hipStream_t s) {
+  if (E.all_n3) return launch_ens_t<NV, JAC, JT, true>(E, kind, s);
+  return launch_ens_t<NV, JAC, JT, false>(E, kind, s);
+}
+
 }  // namespace
+
+fo_status launch_ensemble(const EnsembleLaunch &E, int dtype, int kind, bool want_jac, hipStream_t s) {
+  fo_status st = ensure_tables(E.device);
+  if (st != FO_OK) return st;
+  if (!want_jac) {
+    if (E.nv == 3) return launch_ens_n<3, false, double>(E, kind, s);
+    return launch_ens_n<4, false, double>(E, kind, s);
+  }
+  if (dtype == FO_F32) {
+    if (E.nv == 3) return launch_ens_n<3, true, float>(E, kind, s);
+    return launch_ens_n<4, true, float>(E, kind, s);
+  }
+  if (E.nv == 3) return launch_ens_n<3, true, double>(E, kind, s);
+  return launch_ens_n<4, true, double>(E, kind, s);
+}
 
 fo_status launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
   if (bytes == 0) return FO_OK;

@@ -84,6 +84,7 @@ struct fo_mesh {
   int32_t *slot_off = nullptr;
   int4 *tasks = nullptr;        // [n_tasks] {member, v_begin, v_end, item_begin}
   int32_t n_tasks = 0;
+  std::vector<int4> tasks_host; // host copy, for building ensembles
   int32_t max_slot = 0;         // largest LDS level window (entries) over tasks
   int32_t max_task_verts = 0;
   int64_t *rowptr = nullptr;    // [n_dofs + 1]
@@ -96,6 +97,30 @@ struct fo_mesh {
 };
 
 namespace fo {
+// One member of a batched ensemble launch: its mesh view, outputs and LDS window sizes.
+struct EnsembleMember {
+  MeshView view;
+  const double *U;
+  double *R;
+  void *J;
+  int32_t max_slot;
+  int32_t max_tv;
+};
+
+struct EnsembleLaunch {
+  const EnsembleMember *members;   // device [n_members]
+  const int4 *tasks;               // device [n_tasks], .x = member index
+  int32_t n_tasks;
+  int *counter;                    // device work counter (16 bytes)
+  int32_t nv;
+  bool all_n3;
+  int32_t max_slot, max_tv;
+  int32_t n_cu;
+  int device;
+};
+
+fo_status launch_ensemble(const EnsembleLaunch &E, int dtype, int kind, bool want_jac, hipStream_t s);
+
 // Kernel launchers (fo_assemble.hip, fo_mesh_kernels.hip)
 fo_status launch_pattern(const fo_mesh *m, hipStream_t s);
 fo_status launch_assemble(const fo_mesh *m, const double *U, double *R, void *J, int dtype,

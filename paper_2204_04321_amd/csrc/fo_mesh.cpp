@@ -282,6 +282,7 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   mv.item_vtx = m->item_vtx;
   mv.slot_off = m->slot_off;
   m->n_tasks = int32_t(tasks.size());
+  m->tasks_host = tasks;
   m->max_slot = max_slot;
   m->max_task_verts = max_tv;
   mv.rho_g = d->rho * d->g;
