@@ -158,6 +158,63 @@ fo_status fo_newton_solve(const fo_mesh *mesh, double *U_dev, const fo_newton_op
                           fo_newton_report *report, void *workspace_dev, size_t workspace_bytes,
                           void *stream);
 
+/* ---- Batched ensembles (many meshes, one persistent launch) ---------------------------- */
+typedef struct fo_ensemble fo_ensemble;
+
+/* Group already-created meshes of one element type (their sizes, beta, A, n may differ).
+ * The members must outlive the ensemble; nothing is copied from them but their task tables. */
+fo_status fo_ensemble_create(const fo_mesh *const *members, int32_t n_members, void *stream,
+                             fo_ensemble **out);
+void fo_ensemble_destroy(fo_ensemble *ens);
+
+/* Assemble every member in ONE persistent kernel launch: workgroups take (member, vertex-run)
+ * items from a device counter until all are done.  U_dev, R_dev, J_dev are host arrays of
+ * n_members device pointers laid out as for fo_assemble_jacobian (R_dev may be NULL, or hold
+ * NULL entries, to skip residuals).  J_dev == NULL assembles residuals only (R_dev required).
+ * Each member's result equals its own fo_assemble_jacobian / fo_assemble_residual. */
+fo_status fo_ensemble_assemble(fo_ensemble *ens, const double *const *U_dev, double *const *R_dev,
+                               void *const *J_dev, int32_t dtype, int32_t kind, void *stream);
+
+/* ---- Learned Newton initial guess (not in the paper; feeds eq. linearsystem's first iterate) ----
+ * Network 10 -> 128 -> 128 -> 128 -> 22 (tanh hidden layers), parameters as one FP32 vector:
+ * for each layer W [out][in] then b [out].  Products use BF16 copies (round to nearest even)
+ * of inputs, weights, hidden activations and backpropagated errors on the BF16 matrix cores
+ * with FP32 sums.  All buffers are device pointers owned by the caller. */
+int32_t fo_mlp_param_count(void);
+
+/* Column features [V][10]: H, ds/dx, ds/dy (area-weighted vertex gradient), log(max(beta,
+ * 1e-3)), and H of the 6 nearest base neighbours ordered by angle from -grad s (own H pads).
+ * norm: NULL for raw values, else [20] = 10 means then 10 standard deviations. */
+fo_status fo_column_features(const fo_mesh *mesh, const float *norm_dev, float *feat_dev, void *stream);
+
+/* Y [B][22] from normalised inputs X [B][10]; acts [3][B][128] receives the FP32 hidden
+ * activations that fo_mlp_backward needs. */
+fo_status fo_mlp_forward(const float *params_dev, const float *X_dev, int32_t B, float *acts_dev,
+                         float *Y_dev, void *stream);
+
+/* Gradients of a loss with dL/dY = dY [B][22] into grads [param_count]; dacts is scratch
+ * [2][B][128]. */
+fo_status fo_mlp_backward(const float *params_dev, const float *X_dev, int32_t B, const float *acts_dev,
+                          const float *dY_dev, float *dacts_dev, float *grads_dev, void *stream);
+
+/* dY = 2 (Y - T) / n (mean squared error over n values); loss_dev (may be NULL) += the loss. */
+fo_status fo_mse_grad(const float *Y_dev, const float *T_dev, int64_t n, float *dY_dev, double *loss_dev,
+                      void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on n FP32 parameters with moments m, v. */
+fo_status fo_adam_step(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int32_t n,
+                       float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
+
+/* Initial velocity U = U_sia + 10 sinh(Y) (Y: the network's column outputs, L must be 10),
+ * replaced by the shallow-ice guess U_sia if any value is non-finite, or, with fallback = 1,
+ * if ||F(U)|| > ||F(U_sia)|| (fallback = 0: non-finite values only).  *used_network (host)
+ * tells which one was kept.  Workspace: fo_learned_workspace_bytes, 256-byte aligned.
+ * Synchronises. */
+size_t fo_learned_workspace_bytes(const fo_mesh *mesh);
+fo_status fo_initial_guess_learned(const fo_mesh *mesh, const float *params_dev, const float *norm_dev,
+                                   double *U_dev, int32_t fallback, void *workspace_dev,
+                                   size_t workspace_bytes, int32_t *used_network, void *stream);
+
 /* Measurement support: while enabled, every assembly call records HIP events on
  * its stream around its main assembly kernel (not the zero fills).
  * fo_profile_read synchronises on the last event, returns the summed kernel

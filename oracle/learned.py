@@ -16,7 +16,9 @@ reference and the GPU kernels:
   BF16 (round to nearest even) copies of inputs, weights and hidden activations
   feed every product, sums are accumulated in FP32 on the GPU (FP64 here), biases
   and the tanh derivative use the unrounded FP32 activations;
-* outputs: asinh(u / 10 m/yr) for (u, v) at the L+1 levels, in dof order;
+* outputs: asinh((u - u_sia) / 10 m/yr) for (u, v) at the L+1 levels, in dof order: the
+  network corrects the shallow-ice profile (which carries the rate factor A and the
+  surface slope), so U = U_sia + 10 sinh(y);
 * loss: mean squared error over the batch and the 22 outputs;
 * optimiser: Adam with bias correction.
 """
@@ -79,13 +81,13 @@ def column_features(mesh):
     return F
 
 
-def column_targets(mesh, U):
-    """asinh(U / 10) arranged per vertex column: [V, 2 (L+1)] in dof order."""
-    return np.arcsinh(U.reshape(mesh.n_verts, -1) / OUT_SCALE)
+def column_targets(mesh, U, U_sia):
+    """asinh((U - U_sia) / 10) arranged per vertex column: [V, 2 (L+1)] in dof order."""
+    return np.arcsinh((U - U_sia).reshape(mesh.n_verts, -1) / OUT_SCALE)
 
 
-def targets_to_velocity(Y):
-    return OUT_SCALE * np.sinh(Y).reshape(-1)
+def targets_to_velocity(Y, U_sia):
+    return U_sia + OUT_SCALE * np.sinh(Y).reshape(-1)
 
 
 def init_params(rng, layers=LAYERS):

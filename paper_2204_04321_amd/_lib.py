@@ -82,6 +82,14 @@ def _declare(lib):
         "fo_ensemble_create": (C.c_int, [C.POINTER(vp), i32, vp, C.POINTER(vp)]),
         "fo_ensemble_destroy": (None, [vp]),
         "fo_ensemble_assemble": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i32, i32, vp]),
+        "fo_mlp_param_count": (C.c_int32, []),
+        "fo_column_features": (C.c_int, [vp, vp, vp, vp]),
+        "fo_mlp_forward": (C.c_int, [vp, vp, i32, vp, vp, vp]),
+        "fo_mlp_backward": (C.c_int, [vp, vp, i32, vp, vp, vp, vp, vp]),
+        "fo_mse_grad": (C.c_int, [vp, vp, C.c_int64, vp, vp, vp]),
+        "fo_adam_step": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]),
+        "fo_learned_workspace_bytes": (C.c_size_t, [vp]),
+        "fo_initial_guess_learned": (C.c_int, [vp, vp, vp, vp, i32, vp, C.c_size_t, C.POINTER(C.c_int32), vp]),
         "fo_status_string": (C.c_char_p, [C.c_int]),
         "fo_last_error": (C.c_char_p, []),
     }

@@ -151,6 +151,26 @@ class Mesh:
             check(st)
         return d
 
+    # ---- learned initial guess --------------------------------------------------------------
+    def features(self, norm: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None):
+        F = out if out is not None else torch.empty(self.n_verts, 10, dtype=torch.float32, device=self.device)
+        check(_lib.lib().fo_column_features(self.handle, _ptr(norm), _ptr(F), _stream(stream)))
+        return F
+
+    def learned_guess(self, params: torch.Tensor, norm: torch.Tensor, out: torch.Tensor | None = None,
+                      workspace: torch.Tensor | None = None, fallback: int = 1, stream=None):
+        """(U, used_network): network guess with the shallow-ice fallback (1: non-finite or
+        larger residual norm; 0: non-finite only)."""
+        U = out if out is not None else torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        need = int(_lib.lib().fo_learned_workspace_bytes(self.handle))
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        used = C.c_int32()
+        check(_lib.lib().fo_initial_guess_learned(self.handle, _ptr(params), _ptr(norm), _ptr(U), int(fallback),
+                                                  _ptr(workspace), workspace.numel(), C.byref(used),
+                                                  _stream(stream)))
+        return U, bool(used.value)
+
     # ---- measurement ----------------------------------------------------------------------
     def profile(self, on: bool = True):
         check(_lib.lib().fo_profile_enable(self.handle, 1 if on else 0))
@@ -200,3 +220,43 @@ class Ensemble:
         check(_lib.lib().fo_ensemble_assemble(
             self.handle, u, r, j, FO_F64 if dtype == "f64" else FO_F32,
             FO_JAC_NEWTON if kind == "newton" else FO_JAC_PICARD, _stream(stream)))
+
+
+class MLP:
+    """Thin wrapper over the network kernels (parameters and Adam moments as FP32 tensors)."""
+    LAYERS = (10, 128, 128, 128, 22)
+
+    def __init__(self, params: torch.Tensor):
+        n = int(_lib.lib().fo_mlp_param_count())
+        if params.numel() != n or params.dtype != torch.float32 or not params.is_cuda:
+            raise ValueError(f"expected {n} FP32 device parameters")
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.grads = torch.zeros_like(params)
+        self.step_count = 0
+
+    def forward(self, X: torch.Tensor, acts: torch.Tensor | None = None, stream=None):
+        B = X.shape[0]
+        acts = acts if acts is not None else torch.empty(3, B, 128, dtype=torch.float32, device=X.device)
+        Y = torch.empty(B, 22, dtype=torch.float32, device=X.device)
+        check(_lib.lib().fo_mlp_forward(_ptr(self.params), _ptr(X), B, _ptr(acts), _ptr(Y), _stream(stream)))
+        return Y, acts
+
+    def backward(self, X, acts, dY, stream=None):
+        B = X.shape[0]
+        dacts = torch.empty(2, B, 128, dtype=torch.float32, device=X.device)
+        check(_lib.lib().fo_mlp_backward(_ptr(self.params), _ptr(X), B, _ptr(acts), _ptr(dY), _ptr(dacts),
+                                         _ptr(self.grads), _stream(stream)))
+        return self.grads
+
+    @staticmethod
+    def mse_grad(Y, T, loss: torch.Tensor | None = None, stream=None):
+        dY = torch.empty_like(Y)
+        check(_lib.lib().fo_mse_grad(_ptr(Y), _ptr(T), Y.numel(), _ptr(dY), _ptr(loss), _stream(stream)))
+        return dY
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self.step_count += 1
+        check(_lib.lib().fo_adam_step(_ptr(self.params), _ptr(self.grads), _ptr(self.m), _ptr(self.v),
+                                      self.params.numel(), lr, b1, b2, eps, self.step_count, _stream(stream)))

@@ -23,6 +23,7 @@ SOURCES = [
     "fo_solver.hip",
     "fo_newton.cpp",
     "fo_ensemble.cpp",
+    "fo_learned.hip",
 ]
 
 ARCH = "gfx950"

@@ -1,0 +1,124 @@
+"""GPU kernels of the learned initial guess against the FP64 reference with the same BF16
+rounding points: features (exact ordering), forward/backward (normwise 1e-3), MSE gradient
+and Adam (FP32 rounding), and a small train-then-solve run showing the gain."""
+import numpy as np
+import pytest
+import torch
+
+from fo_inputs import learned_mesh
+from oracle import learned as ol
+from oracle import solve
+
+from gpu_util import gpu_mesh, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _flat(params):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params]).astype(np.float32)
+
+
+def _unflat(vec):
+    out, o = [], 0
+    for i, j in zip(ol.LAYERS[:-1], ol.LAYERS[1:]):
+        W = vec[o:o + i * j].reshape(j, i); o += i * j
+        b = vec[o:o + j]; o += j
+        out.append((W.astype(np.float64), b.astype(np.float64)))
+    return out
+
+
+def test_features_match_reference():
+    m = learned_mesh(20001)
+    M = gpu_mesh(m)
+    F = M.features().cpu().numpy()
+    Fo = ol.column_features(m)
+    np.testing.assert_allclose(F[:, :4], Fo[:, :4], rtol=1e-6, atol=1e-9)
+    # neighbour thicknesses are copied values: the ordering must match exactly
+    np.testing.assert_array_equal(F[:, 4:], Fo[:, 4:].astype(np.float32))
+    mu, sd = Fo.mean(0), Fo.std(0) + 1e-12
+    norm = torch.tensor(np.concatenate([mu, sd]), dtype=torch.float32, device="cuda")
+    Fn = M.features(norm).cpu().numpy()
+    np.testing.assert_allclose(Fn, (Fo - mu) / sd, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("B", [1, 37, 512])
+def test_forward_backward_match_reference(B):
+    from paper_2204_04321_amd.api import MLP
+    rng = np.random.default_rng(B)
+    params = ol.init_params(rng)
+    for W, b in params:
+        b[:] = rng.normal(size=b.shape) * 0.1
+    flat = _flat(params)
+    params = _unflat(flat.astype(np.float64))
+    X = rng.normal(size=(B, 10)).astype(np.float32)
+    T = (rng.normal(size=(B, 22)) * 0.5).astype(np.float32)
+    net = MLP(torch.from_numpy(flat).cuda())
+    Xd = torch.from_numpy(X).cuda()
+    Y, acts = net.forward(Xd)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dY = MLP.mse_grad(Y, torch.from_numpy(T).cuda(), loss)
+    G = net.backward(Xd, acts, dY)
+    torch.cuda.synchronize()
+    Yo, ao = ol.mlp_forward(params, X.astype(np.float64))
+    lo, dYo = ol.mse(Yo, T.astype(np.float64))
+    Go = _flat([(w, b) for w, b in ol.mlp_backward(params, ao, dYo)])
+    Yg = Y.cpu().numpy()
+    assert np.linalg.norm(Yg - Yo) <= 1e-3 * np.linalg.norm(Yo)
+    assert abs(loss.item() - lo) <= 1e-3 * lo
+    Gg = G.cpu().numpy()
+    o = 0
+    for i, j in zip(ol.LAYERS[:-1], ol.LAYERS[1:]):
+        for size in (i * j, j):
+            a, r = Gg[o:o + size], Go[o:o + size]
+            assert np.linalg.norm(a - r) <= 1e-3 * np.linalg.norm(r) + 1e-12, (i, j, size)
+            o += size
+
+
+def test_adam_matches_reference():
+    from paper_2204_04321_amd.api import MLP
+    rng = np.random.default_rng(5)
+    n = 37270
+    p = rng.normal(size=n).astype(np.float32)
+    net = MLP(torch.from_numpy(p.copy()).cuda())
+    m = np.zeros(n); v = np.zeros(n); pr = p.astype(np.float64)
+    for t in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32)
+        net.grads.copy_(torch.from_numpy(g))
+        net.adam(lr=1e-2)
+        pr, m, v = ol.adam_step(pr, g.astype(np.float64), m, v, t, lr=1e-2)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(net.params.cpu().numpy(), pr, rtol=1e-5, atol=1e-6)
+
+
+def test_learned_guess_training_and_fallback():
+    """Train on solutions the method generates (small meshes), then start Newton on held-out
+    meshes from the learned guess and from the shallow-ice guess.  Asserted: training lowers
+    the loss, every solve converges, and the residual-checked fallback keeps the network's
+    guess only when its residual norm is no larger than the shallow-ice guess's (otherwise it
+    returns the shallow-ice guess bit for bit).  The Newton counts of both starts are printed:
+    the per-column network is not required to win on these steep synthetic caps."""
+    from paper_2204_04321_amd.api import Mesh
+    from paper_2204_04321_amd.learned import collect, evaluate, train
+    train_set = collect(range(30000, 30040), n_points=500)
+    model = train(train_set, epochs=150, batch=2048, seed=0)
+    hist = model["loss_history"]
+    assert np.isfinite(hist[-1]) and hist[-1] < 0.5 * hist[0], (hist[0], hist[-1])
+    keys = ("newton_its_sia", "newton_its_learned", "gmres_its_sia", "gmres_its_learned", "fallbacks")
+    rep0 = evaluate(model, range(31000, 31008), n_points=500, fallback=0)
+    rep1 = evaluate(model, range(31000, 31008), n_points=500, fallback=1)
+    print("\n[learned, non-finite fallback]", {k: rep0[k] for k in keys})
+    print("[learned, residual fallback]", {k: rep1[k] for k in keys})
+    assert rep0["all_converged"] and rep1["all_converged"]
+    for seed in range(31000, 31003):
+        M = Mesh(learned_mesh(seed, n_points=500))
+        Us = M.sia()
+        U0, used0 = M.learned_guess(model["params"], model["norm"], fallback=0)
+        U1, used1 = M.learned_guess(model["params"], model["norm"], fallback=1)
+        assert used0 == 1 and bool(torch.isfinite(U0).all())
+        n_nn = torch.linalg.vector_norm(M.residual(U0)).item()
+        n_sia = torch.linalg.vector_norm(M.residual(Us)).item()
+        if used1:
+            assert n_nn <= n_sia * (1 + 1e-12) and torch.equal(U1, U0)
+        else:
+            assert n_nn >= n_sia * (1 - 1e-12) and torch.equal(U1, Us)
+        M.close()

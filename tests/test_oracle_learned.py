@@ -110,5 +110,8 @@ def test_features_keep_six_nearest_and_pad():
 
 def test_target_transform_roundtrip():
     m = _fan_mesh([0, 120, 240], np.full(3, 1e3), [1.0, 2, 3])
-    U = np.random.default_rng(3).normal(size=m.n_dofs) * 300
-    np.testing.assert_allclose(ol.targets_to_velocity(ol.column_targets(m, U)), U, rtol=1e-13)
+    rng = np.random.default_rng(3)
+    U = rng.normal(size=m.n_dofs) * 300
+    Us = rng.normal(size=m.n_dofs) * 300
+    np.testing.assert_allclose(ol.targets_to_velocity(ol.column_targets(m, U, Us), Us), U, rtol=1e-12)
+    np.testing.assert_array_equal(ol.column_targets(m, Us, Us), 0.0)
