@@ -181,7 +181,7 @@ def main():
     jb = 8 if args.jdtype == "f64" else 4
     alg = algorithmic_bytes(m, M.nnz, jb)
     achieved = alg / kern_avg_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.jdtype == "f64" else None
     print(f"[bench] {ms_step:.3f} ms/step, assembly kernel {kern_avg_s * 1e3:.3f} ms, "
           f"{achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
 
@@ -211,7 +211,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "assemble_kernel<wedge, jacobian, double>",
+            "kernel": "owner_kernel<wedge, Jacobian, JT, n=3>",
             "kernel_ms": kern_avg_s * 1e3,
             "algorithmic_bytes": alg,
         },
