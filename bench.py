@@ -124,6 +124,43 @@ def ensemble_bench(args):
     print(json.dumps(out))
 
 
+def newton_bench(args):
+    """Damped Newton on the ice-sheet mesh from the shallow-ice guess to ||F|| <= 1e-8 ||F(0)||,
+    once with the FP64 and once with the FP32 preconditioner Jacobian; one JSON line each."""
+    import torch
+
+    from fo_inputs import config1_icesheet
+    from paper_2204_04321_amd.api import Mesh
+    print("[bench] generating ice-sheet mesh", file=sys.stderr, flush=True)
+    m, _ = config1_icesheet()
+    M = Mesh(m)
+    U = torch.zeros(M.n_dofs, dtype=torch.float64, device="cuda")
+    for jdt in ("f64", "f32"):
+        opts = M.newton_opts(jac_dtype=jdt)
+        ws = torch.empty(M.workspace_bytes(opts), dtype=torch.uint8, device="cuda")
+        M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt, max_newton=1)   # first-call effects
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print(f"[bench] newton {jdt}: status {rep['status']} its {rep['newton_its']} gmres {rep['lin_its']} "
+              f"rel {rep['final_rel']:.2e} {wall:.2f} s", file=sys.stderr, flush=True)
+        print(json.dumps({
+            "metric": "Newton solve wall time, FO-Stokes, shallow-ice start, tol 1e-8",
+            "value": wall, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False,
+            "dtype": "f64 (Jacobian values " + jdt + ")", "data": "synthetic",
+            "config": {"workload": "icesheet wedge mesh, 2,487,040 wedges, 2,750,000 dofs; GMRES(100) "
+                                   "with vertical-column block-LU preconditioner, lin_rtol 1e-6, <= 500 its/step",
+                       "jacobian_values": jdt},
+            "status": rep["status"], "newton_its": rep["newton_its"], "gmres_its": rep["lin_its"],
+            "residual_calls": rep["residual_calls"], "jacobian_calls": rep["jacobian_calls"],
+            "final_rel": rep["final_rel"], "ms_total_fill": rep["ms_total_fill"],
+            "ms_prec_construction": rep["ms_prec_construction"], "ms_linear_solve": rep["ms_linear_solve"],
+            "ms_total_solve": rep["ms_total_solve"]}), flush=True)
+    M.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,8 +169,9 @@ def main():
     ap.add_argument("--jdtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-cells", type=int, default=200_000)
-    ap.add_argument("--workload", choices=["icesheet", "ensemble"], default="icesheet",
-                    help="icesheet: the headline single-mesh line; ensemble: the 64-member batch")
+    ap.add_argument("--workload", choices=["icesheet", "ensemble", "newton"], default="icesheet",
+                    help="icesheet: the headline single-mesh line; ensemble: the 64-member batch; "
+                         "newton: Newton solves on the ice-sheet mesh with FP64 and FP32 Jacobians")
     ap.add_argument("--members", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -143,6 +181,9 @@ def main():
 
     if args.workload == "ensemble":
         ensemble_bench(args)
+        return
+    if args.workload == "newton":
+        newton_bench(args)
         return
 
     import numpy as np

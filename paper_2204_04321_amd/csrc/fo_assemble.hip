@@ -154,8 +154,10 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   constexpr int NQ = Elem<NV>::NQ, NQB = Elem<NV>::NQB;
   using AT = JT;   // derivative arithmetic type
   const QTable &Q = kQ[NV == 3 ? 0 : 1];
-  JT *Jw = reinterpret_cast<JT *>(smem);                                                     // [2][max_slot]
-  double *Rw = reinterpret_cast<double *>(smem + (JAC ? 2 * size_t(max_slot) * sizeof(JT) : 0));  // [2][2 max_tv]
+  // The level windows accumulate in FP64 for either value type: FP32 LDS atomics on this
+  // scatter pattern saturate the LDS data path (measured), FP64 ones do not.
+  double *Jw = reinterpret_cast<double *>(smem);                                               // [2][max_slot]
+  double *Rw = reinterpret_cast<double *>(smem + (JAC ? 2 * size_t(max_slot) * sizeof(double) : 0));  // [2][2 max_tv]
 
   const int lane = threadIdx.x;
   const int vb = task.y, ve = task.z, ib = task.w;
@@ -211,7 +213,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
 
   // ---- zero both level windows -------------------------------------------------------------
   if constexpr (JAC) {
-    for (int e = lane; e < slot_size; e += WAVE) { Jw[e] = JT(0); Jw[max_slot + e] = JT(0); }
+    for (int e = lane; e < slot_size; e += WAVE) { Jw[e] = 0.0; Jw[max_slot + e] = 0.0; }
   }
   for (int e = lane; e < 2 * (ve - vb); e += WAVE) { Rw[e] = 0.0; Rw[2 * max_tv + e] = 0.0; }
 
@@ -352,24 +354,25 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
       Rt1 = fma(s2, gt1, fma(gvy, nt, Rt1));
       if constexpr (JAC) {
         // row side: 2 mu W times the row node's gradient (with the constant factors of
-        // d(eps_c . grad N_a)/dU), and 2 mu' W times its strain projection
-        AT RX[2][9];
+        // d(eps_c . grad N_a)/dU folded into 2x copies here and 1/2 copies on the column
+        // side; all scalings are exact), and 2 mu' W times its strain projection
+        AT RA[2][7];
         {
           const AT s2a = AT(s2), t2a = AT(t2);
           const AT ax[2] = {AT(abx), AT(atx)}, ay[2] = {AT(aby), AT(aty)}, az[2] = {AT(abz), AT(atz)};
           const AT g0[2] = {AT(gb0), AT(gt0)}, g1[2] = {AT(gb1), AT(gt1)};
 #pragma unroll
           for (int a = 0; a < 2; ++a) {
-            const AT Ax = s2a * ax[a], Ay = s2a * ay[a], Az = s2a * az[a];
-            RX[a][0] = Ax + Ax;        RX[a][1] = AT(0.5) * Ay; RX[a][2] = AT(0.5) * Az;
-            RX[a][3] = Ax;             RX[a][4] = Ay;           RX[a][5] = AT(0.5) * Ax;
-            RX[a][6] = Ay + Ay;        RX[a][7] = t2a * g0[a];  RX[a][8] = t2a * g1[a];
+            const AT Ax = s2a * ax[a], Ay = s2a * ay[a];
+            RA[a][0] = Ax; RA[a][1] = Ay; RA[a][2] = s2a * az[a];
+            RA[a][3] = Ax + Ax; RA[a][4] = Ay + Ay;
+            RA[a][5] = t2a * g0[a]; RA[a][6] = t2a * g1[a];
           }
         }
         // column side in the derivative type: d(grad N_b) and d(eps_e^2) along (b, u|v)
-        const AT pxa = AT(px), pya = AT(py), iza = AT(iz);
-        const AT e1xa = AT(e1x), e1ya = AT(e1y), e1za = AT(e1z);
-        const AT e2xa = AT(e2x), e2ya = AT(e2y), e2za = AT(e2z);
+        const AT pxa = AT(px), pya = AT(py), izh = AT(0.5 * iz);
+        const AT e1xa = AT(e1x), e1ya = AT(e1y), e1z2 = AT(2.0 * e1z);
+        const AT e2xa = AT(e2x), e2ya = AT(e2y), e2z2 = AT(2.0 * e2z);
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
           const AT lxj = AT(lx[j]), lyj = AT(ly[j]), lmj = AT(lam[j]);
@@ -377,17 +380,20 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
           for (int lev = 0; lev < 2; ++lev) {
             const AT ll = AT(lev ? l1 : l0);
             const AT dl = lev ? lmj : -lmj;
-            const AT bx = fma(ll, lxj, dl * pxa), by = fma(ll, lyj, dl * pya), bz = dl * iza;
-            const AT gu = fma(e1xa, bx, fma(e1ya, by, e1za * bz));   // d(eps_e^2)/dU_(b,u)
-            const AT gv = fma(e2xa, bx, fma(e2ya, by, e2za * bz));   // d(eps_e^2)/dU_(b,v)
+            const AT bx = fma(ll, lxj, dl * pxa), by = fma(ll, lyj, dl * pya), bzh = dl * izh;
+            const AT bxh = AT(0.5) * bx, byh = AT(0.5) * by;
+            const AT gu = fma(e1xa, bx, fma(e1ya, by, e1z2 * bzh));   // d(eps_e^2)/dU_(b,u)
+            const AT gv = fma(e2xa, bx, fma(e2ya, by, e2z2 * bzh));   // d(eps_e^2)/dU_(b,v)
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
               AT &uu = Jx[a][0][0][j][lev], &uv = Jx[a][0][1][j][lev];
               AT &vu = Jx[a][1][0][j][lev], &vv = Jx[a][1][1][j][lev];
-              uu = fma(RX[a][0], bx, uu); uu = fma(RX[a][1], by, uu); uu = fma(RX[a][2], bz, uu); uu = fma(RX[a][7], gu, uu);
-              uv = fma(RX[a][3], by, uv); uv = fma(RX[a][1], bx, uv); uv = fma(RX[a][7], gv, uv);
-              vu = fma(RX[a][4], bx, vu); vu = fma(RX[a][5], by, vu); vu = fma(RX[a][8], gu, vu);
-              vv = fma(RX[a][5], bx, vv); vv = fma(RX[a][6], by, vv); vv = fma(RX[a][2], bz, vv); vv = fma(RX[a][8], gv, vv);
+              const AT Ax = RA[a][0], Ay = RA[a][1], Az = RA[a][2], Ax2 = RA[a][3], Ay2 = RA[a][4];
+              const AT T0 = RA[a][5], T1 = RA[a][6];
+              uu = fma(Ax2, bx, uu); uu = fma(Ay, byh, uu); uu = fma(Az, bzh, uu); uu = fma(T0, gu, uu);
+              uv = fma(Ax, by, uv); uv = fma(Ay, bxh, uv); uv = fma(T0, gv, uv);
+              vu = fma(Ay, bx, vu); vu = fma(Ax, byh, vu); vu = fma(T1, gu, vu);
+              vv = fma(Ax, bxh, vv); vv = fma(Ay2, by, vv); vv = fma(Az, bzh, vv); vv = fma(T1, gv, vv);
             }
           }
         }
@@ -396,19 +402,24 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
 
     // ---- bed friction on the lower face of the bottom layer (uniform branch) -------------
     if (k == 0) {
-      double bx_[NV], by_[NV], bb_[NV], bH_[NV], bs_[NV], be[NV];
+      double bx_[NV], by_[NV], bb_[NV], bH_[NV], bs_[NV], be[NV], zb[NV], ub[NV], vb_[NV];
       load_geo(bx_, by_, bb_, bH_, bs_);
 #pragma unroll
-      for (int i = 0; i < NV; ++i) be[i] = m.sb[vid[i]].y;
+      for (int i = 0; i < NV; ++i) {
+        be[i] = m.sb[vid[i]].y;
+        zb[i] = bb_[i] + m.sigma[0] * bH_[i];
+        const double2 a0 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1)));
+        ub[i] = a0.x; vb_[i] = a0.y;
+      }
 #pragma unroll
       for (int r = 0; r < NQB; ++r) {
         double txx = 0, txy = 0, txz = 0, tyx = 0, tyy = 0, tyz = 0, br = 0, ur = 0, vr = 0;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
           const double dx = Q.bdlx[r][i], dy = Q.bdly[r][i], lm = Q.blam[r][i];
-          txx += bx_[i] * dx; txy += by_[i] * dx; txz += zlo[i] * dx;
-          tyx += bx_[i] * dy; tyy += by_[i] * dy; tyz += zlo[i] * dy;
-          br += be[i] * lm; ur += ulo[i] * lm; vr += vlo[i] * lm;
+          txx += bx_[i] * dx; txy += by_[i] * dx; txz += zb[i] * dx;
+          tyx += bx_[i] * dy; tyy += by_[i] * dy; tyz += zb[i] * dy;
+          br += be[i] * lm; ur += ub[i] * lm; vr += vb_[i] * lm;
         }
         const double nx = txy * tyz - txz * tyy, ny = txz * tyx - txx * tyz, nz = txx * tyy - txy * tyx;
         const double wb = Q.bw[r] * sqrt(nx * nx + ny * ny + nz * nz) * br;
@@ -439,7 +450,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
         for (int i = 0; i < NV; ++i) rk[i] = m.rank[(int64_t(t) * NV + al) * NV + i];
         const int nlk = nlev(k, L), nl1 = nlev(k + 1, L);
         const int offk = k > 0 ? 1 : 0;     // level k sits at window position 1 unless k = 0
-        JT *Wk = Jw + cur * max_slot + soff, *Wk1 = Jw + nxt * max_slot + soff;
+        double *Wk = Jw + cur * max_slot + soff, *Wk1 = Jw + nxt * max_slot + soff;
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -448,8 +459,8 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
             for (int lev = 0; lev < 2; ++lev)
 #pragma unroll
               for (int d = 0; d < 2; ++d) {
-                lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, JT(Jx[0][c][d][j][lev]));
-                lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, JT(Jx[1][c][d][j][lev]));
+                lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, double(Jx[0][c][d][j][lev]));
+                lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, double(Jx[1][c][d][j][lev]));
               }
       }
     }
@@ -462,31 +473,31 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
       const int nl = nlev(lev_k, L);
       for (int u0 = vb; u0 < ve; u0 += 4) {
         if constexpr (JAC) {
-          JT val[4][3];
+          double val[4][3];
           int nn[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int u = u0 + i;
             nn[i] = u < ve ? 4 * nl * m.deg[u] : 0;
-            const JT *src = Jw + slot * max_slot + (u < ve ? m.slot_off[u] : 0);
+            const double *src = Jw + slot * max_slot + (u < ve ? m.slot_off[u] : 0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               const int e = lane + c * WAVE;
-              val[i][c] = e < nn[i] ? src[e] : JT(0);
+              val[i][c] = e < nn[i] ? src[e] : 0.0;
             }
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int u = u0 + i;
             if (u >= ve) break;
-            JT *src = Jw + slot * max_slot + m.slot_off[u];
+            double *src = Jw + slot * max_slot + m.slot_off[u];
             JT *dst = J + m.colptr[u] + int64_t(4) * m.deg[u] * cumlev(lev_k);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               const int e = lane + c * WAVE;
-              if (e < nn[i]) { dst[e] = val[i][c]; src[e] = JT(0); }
+              if (e < nn[i]) { dst[e] = JT(val[i][c]); src[e] = 0.0; }
             }
-            for (int e = lane + 3 * WAVE; e < nn[i]; e += WAVE) { dst[e] = src[e]; src[e] = JT(0); }
+            for (int e = lane + 3 * WAVE; e < nn[i]; e += WAVE) { dst[e] = JT(src[e]); src[e] = 0.0; }
           }
         }
         if (lane < 8) {
@@ -507,7 +518,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
 }
 
 template <int NV, bool JAC, class JT, bool N3>
-__global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__restrict__ tasks,
+__global__ __launch_bounds__(WAVE, NV == 3 ? 2 : 1) void owner_kernel(MeshView m, const int4 *__restrict__ tasks,
                                                      const double *__restrict__ U, double *__restrict__ R,
                                                      JT *__restrict__ J, int picard, int max_slot,
                                                      int max_tv) {
@@ -518,7 +529,7 @@ __global__ __launch_bounds__(WAVE) void owner_kernel(MeshView m, const int4 *__r
 // Persistent ensemble launch: each workgroup repeatedly takes the next (member, task) pair
 // from a device counter until the combined task table is exhausted (every wave exits).
 template <int NV, bool JAC, class JT, bool N3>
-__global__ __launch_bounds__(WAVE) void ensemble_kernel(const EnsembleMember *__restrict__ mem,
+__global__ __launch_bounds__(WAVE, NV == 3 ? 2 : 1) void ensemble_kernel(const EnsembleMember *__restrict__ mem,
                                                         const int4 *__restrict__ tasks, int n_tasks,
                                                         int *__restrict__ counter, int picard) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -560,7 +571,7 @@ fo_status ensure_tables(int device) {
 template <int NV, bool JAC, class JT, bool N3>
 fo_status launch_t(const fo_mesh *mesh, const double *U, double *R, JT *J, int kind, hipStream_t s) {
   const MeshView &m = mesh->view;
-  const size_t lds = (JAC ? 2 * size_t(mesh->max_slot) * sizeof(JT) : 0) +
+  const size_t lds = (JAC ? 2 * size_t(mesh->max_slot) * sizeof(double) : 0) +
                      2 * 2 * size_t(mesh->max_task_verts) * sizeof(double);
   fo_status st = profile_begin(mesh, s);
   if (st != FO_OK) return st;
@@ -579,7 +590,7 @@ fo_status launch_n(const fo_mesh *mesh, const double *U, double *R, JT *J, int k
 
 template <int NV, bool JAC, class JT, bool N3>
 fo_status launch_ens_t(const EnsembleLaunch &E, int kind, hipStream_t s) {
-  const size_t lds = (JAC ? 2 * size_t(E.max_slot) * sizeof(JT) : 0) + 2 * 2 * size_t(E.max_tv) * sizeof(double);
+  const size_t lds = (JAC ? 2 * size_t(E.max_slot) * sizeof(double) : 0) + 2 * 2 * size_t(E.max_tv) * sizeof(double);
   auto kern = ensemble_kernel<NV, JAC, JT, N3>;
   int per_cu = 0;
   FO_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVE, lds));
