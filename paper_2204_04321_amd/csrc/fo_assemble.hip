@@ -22,6 +22,12 @@
 // scheduling.  Each cell is evaluated by each of its vertex columns (3 or 4
 // times) in exchange.
 //
+// Wedge kernels run two waves per SIMD (256 registers per lane, a few per-layer spills).
+// Their tangents are accumulated in factorised form (per row node and component pair:
+// two weighted sums of the row coefficients and one projection per triangle point), and
+// the twelve column blocks are formed once per layer; the level windows are FP64 for
+// either Jacobian value type.
+//
 // CSR slot of row (v, level kr, comp c) and column (vertex of rank r in v's sorted
 // neighbour list, level kc, comp d): colptr[v] + 4 D_v cumlev(kr) + c 2 nlev(kr) D_v
 // + r 2 nlev(kr) + 2 (kc - max(kr-1, 0)) + d.
@@ -121,10 +127,11 @@ __device__ __forceinline__ double rcp64(double x) {
 // x^(-1/3) for x > 0: single-precision exp2/log2 estimate (~1e-7) refined by two Newton
 // steps on y^-3 = x, y <- y (4 - x y^3) / 3 (quadratic convergence to double precision).
 __device__ __forceinline__ double rcbrt64(double x) {
-  double y = double(__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(float(x)) * (1.0f / 3.0f)));
-  y = y * (4.0 - x * (y * y * y)) * (1.0 / 3.0);
-  y = y * (4.0 - x * (y * y * y)) * (1.0 / 3.0);
-  return y;
+  const double y = double(__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(float(x)) * (1.0f / 3.0f)));
+  // one third-order step: with r = 1 - x y^3, x^(-1/3) = y (1 - r)^(-1/3)
+  // = y (1 + r/3 + 2 r^2/9 + O(r^3)), and |r| ~ 1e-7 leaves O(1e-21)
+  const double r = fma(-x, y * y * y, 1.0);
+  return fma(y * r, fma(2.0 / 9.0, r, 1.0 / 3.0), y);
 }
 
 template <class T>
@@ -211,6 +218,17 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     ly_al = sel4(al, lyc[0], lyc[1], lyc[2], 0.0);
   }
 
+  // metadata of the task's vertex columns, one per lane (a task has at most 64 columns)
+  const int nvt = ve - vb;
+  int my_deg = 0, my_soff = 0, my_col_lo = 0, my_col_hi = 0;
+  if (lane < nvt) {
+    my_deg = m.deg[vb + lane];
+    my_soff = m.slot_off[vb + lane];
+    const int64_t c = m.colptr[vb + lane];
+    my_col_lo = int(uint32_t(uint64_t(c)));
+    my_col_hi = int(uint32_t(uint64_t(c) >> 32));
+  }
+
   // ---- zero both level windows -------------------------------------------------------------
   if constexpr (JAC) {
     for (int e = lane; e < slot_size; e += WAVE) { Jw[e] = 0.0; Jw[max_slot + e] = 0.0; }
@@ -267,137 +285,245 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
             for (int j = 0; j < NV; ++j) { Jx[a][c][d][j][0] = AT(0); Jx[a][c][d][j][1] = AT(0); }
     }
 
+    if constexpr (NV == 3) {
+      // Wedges.  The residual-only kernel runs the same loop without the tangents, so
+      // both kernels produce the same residual bits.  The tangents are accumulated in
+      // factorised form.  Every tangent
+      // entry is sum_q L_q . b_q, where L_q (3 numbers per row node a and component pair
+      // cd) depends on the row only and b_q is the column node's gradient.  For a wedge
+      // column j, b = l0 h_j - lam_j p at the lower level and l1 h_j + lam_j p at the
+      // upper one, with h_j = (dN_j/dx, dN_j/dy, 0) constant over the cell and
+      // p = (d zeta/dx, d zeta/dy, d zeta/dz) the same for all j.  So it suffices to sum
+      // l0 L and L (x, y parts) over all points, and L . p per triangle point; the six
+      // column blocks are formed after the loop.
+      AT FA[2][4][2], FH[2][4][2], FB[2][4][3];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int cd = 0; cd < 4; ++cd) {
+          FA[a][cd][0] = FA[a][cd][1] = AT(0);
+          FH[a][cd][0] = FH[a][cd][1] = AT(0);
+          FB[a][cd][0] = FB[a][cd][1] = FB[a][cd][2] = AT(0);
+        }
+#pragma unroll
+      for (int tp = 0; tp < 3; ++tp) {
+        // the two points above triangle point tp share lam, z_zeta and the u, v increments
+        double zze = 0, dum = 0, dvm = 0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          const double li = Q.lam[tp][i];
+          zze = fma(li, dz[i], zze);
+          dum = fma(li, du[i], dum);
+          dvm = fma(li, dv[i], dvm);
+        }
+        const double iz = rcp64(zze);
+        const double lam_a = sel4(al, Q.lam[tp][0], Q.lam[tp][1], Q.lam[tp][2], 0.0);
+        const double uz = iz * dum, vz = iz * dvm;
 #pragma unroll 1
-    for (int q = 0; q < NQ; ++q) {
-      const double zeta = Q.zeta[q], l0 = 1.0 - zeta, l1 = zeta;
-      double lam[NV], lx[NV], ly[NV];
-      double det, sx, sy;
-#pragma unroll
-      for (int i = 0; i < NV; ++i) lam[i] = Q.lam[q][i];
-      if constexpr (NV == 3) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) { lx[i] = lxc[i]; ly[i] = lyc[i]; }
-        det = detc; sx = sxc; sy = syc;
-      } else {
-        double x_xi = 0, x_eta = 0, y_xi = 0, y_eta = 0;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-          x_xi += xl[i] * Q.dlx[q][i]; x_eta += xl[i] * Q.dly[q][i];
-          y_xi += yl[i] * Q.dlx[q][i]; y_eta += yl[i] * Q.dly[q][i];
-        }
-        det = x_xi * y_eta - x_eta * y_xi;
-        const double iG = rcp64(det);
-        const double i00 = y_eta * iG, i01 = -x_eta * iG, i10 = -y_xi * iG, i11 = x_xi * iG;
-        sx = 0; sy = 0;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-          lx[i] = Q.dlx[q][i] * i00 + Q.dly[q][i] * i10;
-          ly[i] = Q.dlx[q][i] * i01 + Q.dly[q][i] * i11;
-          sx += su[i] * lx[i];
-          sy += su[i] * ly[i];
-        }
-      }
-      // vertical map: z_zeta and the slopes of z along x, y at fixed zeta
-      double zze = 0, zxs, zys, ucx, ucy, vcx, vcy, dum = 0, dvm = 0;
-#pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        zze = fma(lam[i], dz[i], zze);
-        dum = fma(lam[i], du[i], dum);
-        dvm = fma(lam[i], dv[i], dvm);
-      }
-      if constexpr (NV == 3) {
-        zxs = fma(zeta, HS[1], HS[0]); zys = fma(zeta, HS[3], HS[2]);
-        ucx = fma(zeta, HS[5], HS[4]); ucy = fma(zeta, HS[7], HS[6]);
-        vcx = fma(zeta, HS[9], HS[8]); vcy = fma(zeta, HS[11], HS[10]);
-      } else {
-        zxs = zys = ucx = ucy = vcx = vcy = 0;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-          const double zc = fma(zeta, dz[i], zlo[i]);
-          const double uc = fma(zeta, du[i], ulo[i]);
-          const double vc = fma(zeta, dv[i], vlo[i]);
-          zxs = fma(lx[i], zc, zxs); zys = fma(ly[i], zc, zys);
-          ucx = fma(lx[i], uc, ucx); ucy = fma(ly[i], uc, ucy);
-          vcx = fma(lx[i], vc, vcx); vcy = fma(ly[i], vc, vcy);
-        }
-      }
-      const double iz = rcp64(zze);
-      const double px = -zxs * iz, py = -zys * iz;        // d zeta / dx, d zeta / dy
-      const double W = Q.w[q] * det * zze;
-      // velocity gradient, strain rates, viscosity
-      const double ux = ucx + px * dum, uy = ucy + py * dum, uz = iz * dum;
-      const double vx = vcx + px * dvm, vy = vcy + py * dvm, vz = iz * dvm;
-      const double exx = ux, eyy = vy, exy = 0.5 * (uy + vx), exz = 0.5 * uz, eyz = 0.5 * vz;
-      const double qq = exx * exx + eyy * eyy + exx * eyy + exy * exy + exz * exz + eyz * eyz;
-      const double qe = qq + m.eps0_sq;
-      double mu;
-      if constexpr (N3) mu = m.visc_pref * rcbrt64(qe);
-      else mu = m.visc_pref * pow(qe, m.visc_exp);
-      const double s2 = 2.0 * mu * W;
-      const double t2 = picard ? 0.0 : 2.0 * (m.visc_exp * mu * rcp64(qe)) * W;
-      const double e1x = 2.0 * exx + eyy, e1y = exy, e1z = exz;
-      const double e2x = exy, e2y = exx + 2.0 * eyy, e2z = eyz;
-      const double gvx = W * m.rho_g * sx, gvy = W * m.rho_g * sy;
-      // v's own nodes in this cell: corner al at the lower and upper level
-      const double lam_a = sel4(al, lam[0], lam[1], lam[2], lam[NV - 1]);
-      double lxa, lya;
-      if constexpr (NV == 3) { lxa = lx_al; lya = ly_al; }
-      else { lxa = sel4(al, lx[0], lx[1], lx[2], lx[NV - 1]); lya = sel4(al, ly[0], ly[1], ly[2], ly[NV - 1]); }
-      const double abx = l0 * lxa - lam_a * px, aby = l0 * lya - lam_a * py, abz = -lam_a * iz;
-      const double atx = l1 * lxa + lam_a * px, aty = l1 * lya + lam_a * py, atz = lam_a * iz;
-      const double gb0 = e1x * abx + e1y * aby + e1z * abz, gb1 = e2x * abx + e2y * aby + e2z * abz;
-      const double gt0 = e1x * atx + e1y * aty + e1z * atz, gt1 = e2x * atx + e2y * aty + e2z * atz;
-      const double nb = lam_a * l0, nt = lam_a * l1;     // v's basis functions at q
-      Rb0 = fma(s2, gb0, fma(gvx, nb, Rb0));
-      Rb1 = fma(s2, gb1, fma(gvy, nb, Rb1));
-      Rt0 = fma(s2, gt0, fma(gvx, nt, Rt0));
-      Rt1 = fma(s2, gt1, fma(gvy, nt, Rt1));
-      if constexpr (JAC) {
-        // row side: 2 mu W times the row node's gradient (with the constant factors of
-        // d(eps_c . grad N_a)/dU folded into 2x copies here and 1/2 copies on the column
-        // side; all scalings are exact), and 2 mu' W times its strain projection
-        AT RA[2][7];
-        {
-          const AT s2a = AT(s2), t2a = AT(t2);
-          const AT ax[2] = {AT(abx), AT(atx)}, ay[2] = {AT(aby), AT(aty)}, az[2] = {AT(abz), AT(atz)};
-          const AT g0[2] = {AT(gb0), AT(gt0)}, g1[2] = {AT(gb1), AT(gt1)};
+        for (int zi = 0; zi < 2; ++zi) {
+          const int q = tp + 3 * zi;
+          const double zeta = Q.zeta[q], l0 = 1.0 - zeta, l1 = zeta;
+          const double zxs = fma(zeta, HS[1], HS[0]), zys = fma(zeta, HS[3], HS[2]);
+          const double ucx = fma(zeta, HS[5], HS[4]), ucy = fma(zeta, HS[7], HS[6]);
+          const double vcx = fma(zeta, HS[9], HS[8]), vcy = fma(zeta, HS[11], HS[10]);
+          const double px = -zxs * iz, py = -zys * iz;        // d zeta / dx, d zeta / dy
+          const double W = Q.w[q] * detc * zze;
+          const double ux = ucx + px * dum, uy = ucy + py * dum;
+          const double vx = vcx + px * dvm, vy = vcy + py * dvm;
+          const double exx = ux, eyy = vy, exy = 0.5 * (uy + vx), exz = 0.5 * uz, eyz = 0.5 * vz;
+          const double qq = exx * exx + eyy * eyy + exx * eyy + exy * exy + exz * exz + eyz * eyz;
+          const double qe = qq + m.eps0_sq;
+          double mu;
+          if constexpr (N3) mu = m.visc_pref * rcbrt64(qe);
+          else mu = m.visc_pref * pow(qe, m.visc_exp);
+          const double s2 = 2.0 * mu * W;
+          const double t2 = picard ? 0.0 : 2.0 * (m.visc_exp * mu * rcp64(qe)) * W;
+          const double e1x = 2.0 * exx + eyy, e1y = exy, e1z = exz;
+          const double e2x = exy, e2y = exx + 2.0 * eyy, e2z = eyz;
+          const double gvx = W * m.rho_g * sxc, gvy = W * m.rho_g * syc;
+          const double abx = l0 * lx_al - lam_a * px, aby = l0 * ly_al - lam_a * py, abz = -lam_a * iz;
+          const double atx = l1 * lx_al + lam_a * px, aty = l1 * ly_al + lam_a * py, atz = lam_a * iz;
+          const double gb0 = e1x * abx + e1y * aby + e1z * abz, gb1 = e2x * abx + e2y * aby + e2z * abz;
+          const double gt0 = e1x * atx + e1y * aty + e1z * atz, gt1 = e2x * atx + e2y * aty + e2z * atz;
+          const double nb = lam_a * l0, nt = lam_a * l1;
+          Rb0 = fma(s2, gb0, fma(gvx, nb, Rb0));
+          Rb1 = fma(s2, gb1, fma(gvy, nb, Rb1));
+          Rt0 = fma(s2, gt0, fma(gvx, nt, Rt0));
+          Rt1 = fma(s2, gt1, fma(gvy, nt, Rt1));
+          if constexpr (!JAC) continue;
+          const AT l0a = AT(l0), pxa = AT(px), pya = AT(py), iza = AT(iz);
+          const AT e1xa = AT(e1x), e1ya = AT(e1y), e1za = AT(e1z);
+          const AT e2xa = AT(e2x), e2ya = AT(e2y), e2za = AT(e2z);
 #pragma unroll
           for (int a = 0; a < 2; ++a) {
-            const AT Ax = s2a * ax[a], Ay = s2a * ay[a];
-            RA[a][0] = Ax; RA[a][1] = Ay; RA[a][2] = s2a * az[a];
-            RA[a][3] = Ax + Ax; RA[a][4] = Ay + Ay;
-            RA[a][5] = t2a * g0[a]; RA[a][6] = t2a * g1[a];
-          }
-        }
-        // column side in the derivative type: d(grad N_b) and d(eps_e^2) along (b, u|v)
-        const AT pxa = AT(px), pya = AT(py), izh = AT(0.5 * iz);
-        const AT e1xa = AT(e1x), e1ya = AT(e1y), e1z2 = AT(2.0 * e1z);
-        const AT e2xa = AT(e2x), e2ya = AT(e2y), e2z2 = AT(2.0 * e2z);
+            const AT Ax = AT(s2 * (a ? atx : abx)), Ay = AT(s2 * (a ? aty : aby)), Az = AT(s2 * (a ? atz : abz));
+            const AT T0 = AT(t2 * (a ? gt0 : gb0)), T1 = AT(t2 * (a ? gt1 : gb1));
+            const AT hAx = AT(0.5) * Ax, hAy = AT(0.5) * Ay, hAz = AT(0.5) * Az;
+            // L for uu, uv, vu, vv: coefficients of (bx, by, bz) in d R_(a,c) / d U_(b,d)
+            const AT Lx[4] = {fma(T0, e1xa, Ax + Ax), fma(T0, e2xa, hAy), fma(T1, e1xa, Ay), fma(T1, e2xa, hAx)};
+            const AT Ly[4] = {fma(T0, e1ya, hAy), fma(T0, e2ya, Ax), fma(T1, e1ya, hAx), fma(T1, e2ya, Ay + Ay)};
+            const AT Lz[4] = {fma(T0, e1za, hAz), T0 * e2za, T1 * e1za, fma(T1, e2za, hAz)};
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-          const AT lxj = AT(lx[j]), lyj = AT(ly[j]), lmj = AT(lam[j]);
-#pragma unroll
-          for (int lev = 0; lev < 2; ++lev) {
-            const AT ll = AT(lev ? l1 : l0);
-            const AT dl = lev ? lmj : -lmj;
-            const AT bx = fma(ll, lxj, dl * pxa), by = fma(ll, lyj, dl * pya), bzh = dl * izh;
-            const AT bxh = AT(0.5) * bx, byh = AT(0.5) * by;
-            const AT gu = fma(e1xa, bx, fma(e1ya, by, e1z2 * bzh));   // d(eps_e^2)/dU_(b,u)
-            const AT gv = fma(e2xa, bx, fma(e2ya, by, e2z2 * bzh));   // d(eps_e^2)/dU_(b,v)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-              AT &uu = Jx[a][0][0][j][lev], &uv = Jx[a][0][1][j][lev];
-              AT &vu = Jx[a][1][0][j][lev], &vv = Jx[a][1][1][j][lev];
-              const AT Ax = RA[a][0], Ay = RA[a][1], Az = RA[a][2], Ax2 = RA[a][3], Ay2 = RA[a][4];
-              const AT T0 = RA[a][5], T1 = RA[a][6];
-              uu = fma(Ax2, bx, uu); uu = fma(Ay, byh, uu); uu = fma(Az, bzh, uu); uu = fma(T0, gu, uu);
-              uv = fma(Ax, by, uv); uv = fma(Ay, bxh, uv); uv = fma(T0, gv, uv);
-              vu = fma(Ay, bx, vu); vu = fma(Ax, byh, vu); vu = fma(T1, gu, vu);
-              vv = fma(Ax, bxh, vv); vv = fma(Ay2, by, vv); vv = fma(Az, bzh, vv); vv = fma(T1, gv, vv);
+            for (int cd = 0; cd < 4; ++cd) {
+              FA[a][cd][0] = fma(l0a, Lx[cd], FA[a][cd][0]);
+              FA[a][cd][1] = fma(l0a, Ly[cd], FA[a][cd][1]);
+              FH[a][cd][0] += Lx[cd];
+              FH[a][cd][1] += Ly[cd];
+              FB[a][cd][tp] = fma(Lx[cd], pxa, fma(Ly[cd], pya, fma(Lz[cd], iza, FB[a][cd][tp])));
             }
           }
         }
       }
+      // column blocks: with Lam_j = sum_tp lam_j(tp) FB[tp],
+      // lower level: lx_j FA_x + ly_j FA_y - Lam_j; upper: lx_j (FH - FA)_x + ly_j (FH - FA)_y + Lam_j
+#pragma unroll
+      for (int a = 0; a < (JAC ? 2 : 0); ++a)
+#pragma unroll
+        for (int cd = 0; cd < 4; ++cd) {
+          const AT Ux = FH[a][cd][0] - FA[a][cd][0], Uy = FH[a][cd][1] - FA[a][cd][1];
+#pragma unroll
+          for (int j = 0; j < NV; ++j) {
+            const AT lam = fma(AT(Q.lam[0][j]), FB[a][cd][0],
+                               fma(AT(Q.lam[1][j]), FB[a][cd][1], AT(Q.lam[2][j]) * FB[a][cd][2]));
+            const AT hx = AT(lxc[j]), hy = AT(lyc[j]);
+            Jx[a][cd >> 1][cd & 1][j][0] = fma(hx, FA[a][cd][0], fma(hy, FA[a][cd][1], -lam));
+            Jx[a][cd >> 1][cd & 1][j][1] = fma(hx, Ux, fma(hy, Uy, lam));
+          }
+        }
+    } else {
+#pragma unroll 1
+      for (int q = 0; q < NQ; ++q) {
+        const double zeta = Q.zeta[q], l0 = 1.0 - zeta, l1 = zeta;
+        double lam[NV], lx[NV], ly[NV];
+        double det, sx, sy;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) lam[i] = Q.lam[q][i];
+        if constexpr (NV == 3) {
+#pragma unroll
+          for (int i = 0; i < NV; ++i) { lx[i] = lxc[i]; ly[i] = lyc[i]; }
+          det = detc; sx = sxc; sy = syc;
+        } else {
+          double x_xi = 0, x_eta = 0, y_xi = 0, y_eta = 0;
+#pragma unroll
+          for (int i = 0; i < NV; ++i) {
+            x_xi += xl[i] * Q.dlx[q][i]; x_eta += xl[i] * Q.dly[q][i];
+            y_xi += yl[i] * Q.dlx[q][i]; y_eta += yl[i] * Q.dly[q][i];
+          }
+          det = x_xi * y_eta - x_eta * y_xi;
+          const double iG = rcp64(det);
+          const double i00 = y_eta * iG, i01 = -x_eta * iG, i10 = -y_xi * iG, i11 = x_xi * iG;
+          sx = 0; sy = 0;
+#pragma unroll
+          for (int i = 0; i < NV; ++i) {
+            lx[i] = Q.dlx[q][i] * i00 + Q.dly[q][i] * i10;
+            ly[i] = Q.dlx[q][i] * i01 + Q.dly[q][i] * i11;
+            sx += su[i] * lx[i];
+            sy += su[i] * ly[i];
+          }
+        }
+        // vertical map: z_zeta and the slopes of z along x, y at fixed zeta
+        double zze = 0, zxs, zys, ucx, ucy, vcx, vcy, dum = 0, dvm = 0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          zze = fma(lam[i], dz[i], zze);
+          dum = fma(lam[i], du[i], dum);
+          dvm = fma(lam[i], dv[i], dvm);
+        }
+        if constexpr (NV == 3) {
+          zxs = fma(zeta, HS[1], HS[0]); zys = fma(zeta, HS[3], HS[2]);
+          ucx = fma(zeta, HS[5], HS[4]); ucy = fma(zeta, HS[7], HS[6]);
+          vcx = fma(zeta, HS[9], HS[8]); vcy = fma(zeta, HS[11], HS[10]);
+        } else {
+          zxs = zys = ucx = ucy = vcx = vcy = 0;
+#pragma unroll
+          for (int i = 0; i < NV; ++i) {
+            const double zc = fma(zeta, dz[i], zlo[i]);
+            const double uc = fma(zeta, du[i], ulo[i]);
+            const double vc = fma(zeta, dv[i], vlo[i]);
+            zxs = fma(lx[i], zc, zxs); zys = fma(ly[i], zc, zys);
+            ucx = fma(lx[i], uc, ucx); ucy = fma(ly[i], uc, ucy);
+            vcx = fma(lx[i], vc, vcx); vcy = fma(ly[i], vc, vcy);
+          }
+        }
+        const double iz = rcp64(zze);
+        const double px = -zxs * iz, py = -zys * iz;        // d zeta / dx, d zeta / dy
+        const double W = Q.w[q] * det * zze;
+        // velocity gradient, strain rates, viscosity
+        const double ux = ucx + px * dum, uy = ucy + py * dum, uz = iz * dum;
+        const double vx = vcx + px * dvm, vy = vcy + py * dvm, vz = iz * dvm;
+        const double exx = ux, eyy = vy, exy = 0.5 * (uy + vx), exz = 0.5 * uz, eyz = 0.5 * vz;
+        const double qq = exx * exx + eyy * eyy + exx * eyy + exy * exy + exz * exz + eyz * eyz;
+        const double qe = qq + m.eps0_sq;
+        double mu;
+        if constexpr (N3) mu = m.visc_pref * rcbrt64(qe);
+        else mu = m.visc_pref * pow(qe, m.visc_exp);
+        const double s2 = 2.0 * mu * W;
+        const double t2 = picard ? 0.0 : 2.0 * (m.visc_exp * mu * rcp64(qe)) * W;
+        const double e1x = 2.0 * exx + eyy, e1y = exy, e1z = exz;
+        const double e2x = exy, e2y = exx + 2.0 * eyy, e2z = eyz;
+        const double gvx = W * m.rho_g * sx, gvy = W * m.rho_g * sy;
+        // v's own nodes in this cell: corner al at the lower and upper level
+        const double lam_a = sel4(al, lam[0], lam[1], lam[2], lam[NV - 1]);
+        double lxa, lya;
+        if constexpr (NV == 3) { lxa = lx_al; lya = ly_al; }
+        else { lxa = sel4(al, lx[0], lx[1], lx[2], lx[NV - 1]); lya = sel4(al, ly[0], ly[1], ly[2], ly[NV - 1]); }
+        const double abx = l0 * lxa - lam_a * px, aby = l0 * lya - lam_a * py, abz = -lam_a * iz;
+        const double atx = l1 * lxa + lam_a * px, aty = l1 * lya + lam_a * py, atz = lam_a * iz;
+        const double gb0 = e1x * abx + e1y * aby + e1z * abz, gb1 = e2x * abx + e2y * aby + e2z * abz;
+        const double gt0 = e1x * atx + e1y * aty + e1z * atz, gt1 = e2x * atx + e2y * aty + e2z * atz;
+        const double nb = lam_a * l0, nt = lam_a * l1;     // v's basis functions at q
+        Rb0 = fma(s2, gb0, fma(gvx, nb, Rb0));
+        Rb1 = fma(s2, gb1, fma(gvy, nb, Rb1));
+        Rt0 = fma(s2, gt0, fma(gvx, nt, Rt0));
+        Rt1 = fma(s2, gt1, fma(gvy, nt, Rt1));
+        if constexpr (JAC) {
+          // row side: 2 mu W times the row node's gradient (with the constant factors of
+          // d(eps_c . grad N_a)/dU folded into 2x copies here and 1/2 copies on the column
+          // side; all scalings are exact), and 2 mu' W times its strain projection
+          AT RA[2][7];
+          {
+            const AT s2a = AT(s2), t2a = AT(t2);
+            const AT ax[2] = {AT(abx), AT(atx)}, ay[2] = {AT(aby), AT(aty)}, az[2] = {AT(abz), AT(atz)};
+            const AT g0[2] = {AT(gb0), AT(gt0)}, g1[2] = {AT(gb1), AT(gt1)};
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const AT Ax = s2a * ax[a], Ay = s2a * ay[a];
+              RA[a][0] = Ax; RA[a][1] = Ay; RA[a][2] = s2a * az[a];
+              RA[a][3] = Ax + Ax; RA[a][4] = Ay + Ay;
+              RA[a][5] = t2a * g0[a]; RA[a][6] = t2a * g1[a];
+            }
+          }
+          // column side in the derivative type: d(grad N_b) and d(eps_e^2) along (b, u|v)
+          const AT pxa = AT(px), pya = AT(py), izh = AT(0.5 * iz);
+          const AT e1xa = AT(e1x), e1ya = AT(e1y), e1z2 = AT(2.0 * e1z);
+          const AT e2xa = AT(e2x), e2ya = AT(e2y), e2z2 = AT(2.0 * e2z);
+#pragma unroll
+          for (int j = 0; j < NV; ++j) {
+            const AT lxj = AT(lx[j]), lyj = AT(ly[j]), lmj = AT(lam[j]);
+#pragma unroll
+            for (int lev = 0; lev < 2; ++lev) {
+              const AT ll = AT(lev ? l1 : l0);
+              const AT dl = lev ? lmj : -lmj;
+              const AT bx = fma(ll, lxj, dl * pxa), by = fma(ll, lyj, dl * pya), bzh = dl * izh;
+              const AT bxh = AT(0.5) * bx, byh = AT(0.5) * by;
+              const AT gu = fma(e1xa, bx, fma(e1ya, by, e1z2 * bzh));   // d(eps_e^2)/dU_(b,u)
+              const AT gv = fma(e2xa, bx, fma(e2ya, by, e2z2 * bzh));   // d(eps_e^2)/dU_(b,v)
+#pragma unroll
+              for (int a = 0; a < 2; ++a) {
+                AT &uu = Jx[a][0][0][j][lev], &uv = Jx[a][0][1][j][lev];
+                AT &vu = Jx[a][1][0][j][lev], &vv = Jx[a][1][1][j][lev];
+                const AT Ax = RA[a][0], Ay = RA[a][1], Az = RA[a][2], Ax2 = RA[a][3], Ay2 = RA[a][4];
+                const AT T0 = RA[a][5], T1 = RA[a][6];
+                uu = fma(Ax2, bx, uu); uu = fma(Ay, byh, uu); uu = fma(Az, bzh, uu); uu = fma(T0, gu, uu);
+                uv = fma(Ax, by, uv); uv = fma(Ay, bxh, uv); uv = fma(T0, gv, uv);
+                vu = fma(Ay, bx, vu); vu = fma(Ax, byh, vu); vu = fma(T1, gu, vu);
+                vv = fma(Ax, bxh, vv); vv = fma(Ay2, by, vv); vv = fma(Az, bzh, vv); vv = fma(T1, gv, vv);
+              }
+            }
+          }
+        }
+      }
+  
     }
 
     // ---- bed friction on the lower face of the bottom layer (uniform branch) -------------
@@ -471,27 +597,33 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     // the first global store, so one LDS latency is exposed per batch, not per chunk.
     auto flush = [&](int lev_k, int slot) {
       const int nl = nlev(lev_k, L);
-      for (int u0 = vb; u0 < ve; u0 += 4) {
+      const int lk = cumlev(lev_k);
+      const double *wsrc = Jw + slot * max_slot;
+      double *wdst = Jw + slot * max_slot;
+      for (int i0 = 0; i0 < nvt; i0 += 4) {
         if constexpr (JAC) {
           double val[4][3];
-          int nn[4];
+          int nn[4], so[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int u = u0 + i;
-            nn[i] = u < ve ? 4 * nl * m.deg[u] : 0;
-            const double *src = Jw + slot * max_slot + (u < ve ? m.slot_off[u] : 0);
+            const int ii = i0 + i < nvt ? i0 + i : nvt - 1;
+            so[i] = __builtin_amdgcn_readlane(my_soff, ii);
+            nn[i] = i0 + i < nvt ? 4 * nl * __builtin_amdgcn_readlane(my_deg, ii) : 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               const int e = lane + c * WAVE;
-              val[i][c] = e < nn[i] ? src[e] : 0.0;
+              val[i][c] = wsrc[so[i] + (e < nn[i] ? e : 0)];
             }
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int u = u0 + i;
-            if (u >= ve) break;
-            double *src = Jw + slot * max_slot + m.slot_off[u];
-            JT *dst = J + m.colptr[u] + int64_t(4) * m.deg[u] * cumlev(lev_k);
+            if (i0 + i >= nvt) break;
+            const int ii = i0 + i;
+            const int D = __builtin_amdgcn_readlane(my_deg, ii);
+            const int64_t col = int64_t(unsigned(__builtin_amdgcn_readlane(my_col_lo, ii))) |
+                                (int64_t(__builtin_amdgcn_readlane(my_col_hi, ii)) << 32);
+            JT *dst = J + col + int64_t(4) * D * lk;
+            double *src = wdst + so[i];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               const int e = lane + c * WAVE;
@@ -500,13 +632,11 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
             for (int e = lane + 3 * WAVE; e < nn[i]; e += WAVE) { dst[e] = JT(src[e]); src[e] = 0.0; }
           }
         }
-        if (lane < 8) {
-          const int u = u0 + (lane >> 1);
-          if (u < ve) {
-            double *rs = Rw + slot * 2 * max_tv + 2 * (u - vb) + (lane & 1);
-            if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + (lane & 1)] = *rs;
-            *rs = 0.0;
-          }
+        if (lane < 8 && i0 + (lane >> 1) < nvt) {
+          const int u = vb + i0 + (lane >> 1);
+          double *rs = Rw + slot * 2 * max_tv + 2 * (u - vb) + (lane & 1);
+          if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + (lane & 1)] = *rs;
+          *rs = 0.0;
         }
       }
     };
