@@ -105,7 +105,10 @@ fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b
       double *vj = V + int64_t(j) * n;
       if ((st = colblock_apply(c.m, fac, vj, z, c.s)) != FO_OK) return st;
       if ((st = spmv(c.m, Jv, o->jac_dtype, z, w, c.s)) != FO_OK) return st;
-      // classical Gram-Schmidt, twice
+      // classical Gram-Schmidt with one selective reorthogonalisation.  A pass that
+      // shrinks w by kappa = ||w|| / ||w - V h|| leaves it orthogonal to V only to about
+      // eps kappa, and the norm from ||w - V h||^2 = ||w||^2 - ||h||^2 is then good to
+      // about eps kappa^2; the second pass runs when kappa > 1e3 (both bounds near 1e-10)
       double hsum[512];
       for (int pass = 0; pass < 2; ++pass) {
         if ((st = multidot(n, V, n, j + 1, w, c.dptr(c.L.partial), c.dptr(c.L.dots), c.s)) != FO_OK) return st;
@@ -113,13 +116,11 @@ fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b
         FO_HIP_TRY(hipMemcpyAsync(c.host, c.dptr(c.L.dots), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.s));
         FO_HIP_TRY(hipStreamSynchronize(c.s));
         for (int i = 0; i <= j; ++i) hsum[i] = (pass == 0 ? 0.0 : hsum[i]) + c.host[i];
-        if (pass == 1) {
-          // ||w||^2 after the second projection = ||w_before||^2 - ||h2||^2
-          double h2 = 0.0;
-          for (int i = 0; i <= j; ++i) h2 += c.host[i] * c.host[i];
-          const double wn2 = c.host[j + 1] - h2;
-          H[size_t(j + 1) * mres + j] = std::sqrt(wn2 > 0 ? wn2 : 0.0);
-        }
+        double h2 = 0.0;
+        for (int i = 0; i <= j; ++i) h2 += c.host[i] * c.host[i];
+        const double wn2 = c.host[j + 1] - h2;   // ||w||^2 after this projection
+        H[size_t(j + 1) * mres + j] = std::sqrt(wn2 > 0 ? wn2 : 0.0);
+        if (pass == 0 && wn2 > 1e-6 * c.host[j + 1]) break;
       }
       for (int i = 0; i <= j; ++i) H[size_t(i) * mres + j] = hsum[i];
       const double hn = H[size_t(j + 1) * mres + j];

@@ -18,24 +18,37 @@ namespace {
 __device__ __forceinline__ int nlev(int k, int L) { return (k == 0 || k == L) ? 2 : 3; }
 __device__ __forceinline__ int cumlev(int k) { return k == 0 ? 0 : 3 * k - 1; }
 
-constexpr int SPMV_LANES = 8;   // lanes per CSR row
+constexpr int SPMV_LANES = 8;   // lanes per node (pair of CSR rows)
 
+// The two rows of a node (components u and v) have the same column list (the pattern
+// couples full 2x2 dof blocks), and the second row follows the first in the CSR arrays:
+// each lane group reads a column index and x entry once for both rows.
 template <class JT>
-__global__ __launch_bounds__(256) void spmv_kernel(int64_t n, const int64_t *__restrict__ rowptr,
+__global__ __launch_bounds__(256) void spmv_kernel(int64_t n_nodes, const int64_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ colidx,
                                                    const JT *__restrict__ vals,
                                                    const double *__restrict__ x, double *__restrict__ y) {
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t row = gid / SPMV_LANES;
+  const int64_t node = gid / SPMV_LANES;
   const int sub = int(gid % SPMV_LANES);
-  double acc = 0.0;
-  if (row < n) {
-    const int64_t b = rowptr[row], e = rowptr[row + 1];
-    for (int64_t p = b + sub; p < e; p += SPMV_LANES) acc += double(vals[p]) * x[colidx[p]];
+  double a0 = 0.0, a1 = 0.0;
+  if (node < n_nodes) {
+    const int64_t b = rowptr[2 * node], len = rowptr[2 * node + 1] - b;
+    for (int64_t p = b + sub; p < b + len; p += SPMV_LANES) {
+      const double xv = x[colidx[p]];
+      a0 = fma(double(vals[p]), xv, a0);
+      a1 = fma(double(vals[p + len]), xv, a1);
+    }
   }
 #pragma unroll
-  for (int off = SPMV_LANES / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, SPMV_LANES);
-  if (row < n && sub == 0) y[row] = acc;
+  for (int off = SPMV_LANES / 2; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off, SPMV_LANES);
+    a1 += __shfl_xor(a1, off, SPMV_LANES);
+  }
+  if (node < n_nodes && sub == 0) {
+    y[2 * node] = a0;
+    y[2 * node + 1] = a1;
+  }
 }
 
 // Block-tridiagonal factor of one vertical line (column v): per level k the inverse
@@ -50,7 +63,7 @@ __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const 
   const int D = m.deg[v];
   const int sr = self_rank[v];
   const int64_t base = m.colptr[v];
-  double *F = fac + int64_t(v) * (L + 1) * 12;
+  const int64_t V = m.V;
   double Sp[4] = {0, 0, 0, 0};      // S_{k-1}^{-1}
   double Upp[4] = {0, 0, 0, 0};     // Up_{k-1}
   for (int k = 0; k <= L; ++k) {
@@ -79,47 +92,49 @@ __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const 
     const double det = Dk[0] * Dk[3] - Dk[1] * Dk[2];
     const double id = 1.0 / det;
     double Si[4] = {Dk[3] * id, -Dk[1] * id, -Dk[2] * id, Dk[0] * id};
-    double *Fk = F + k * 12;
+    double *Fk = fac + int64_t(k) * 12 * V + v;   // field f of level k at Fk[f V]
     for (int i = 0; i < 4; ++i) {
-      Fk[i] = Si[i];
-      Fk[4 + i] = Lo[i];
-      Fk[8 + i] = Up[i];
+      Fk[i * V] = Si[i];
+      Fk[(4 + i) * V] = Lo[i];
+      Fk[(8 + i) * V] = Up[i];
       Sp[i] = Si[i];
       Upp[i] = Up[i];
     }
   }
 }
 
-// z = M^{-1} r for every vertical line (forward then backward block substitution).
+// z = M^{-1} r for every vertical line (forward then backward block substitution).  The
+// factors are stored level-major with the vertex index fastest, so a wave's loads of one
+// factor field are contiguous.
 __global__ __launch_bounds__(128) void colblock_apply_kernel(int V, int L, const double *__restrict__ fac,
                                                              const double *__restrict__ r,
                                                              double *__restrict__ z) {
   const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  const double *F = fac + int64_t(v) * (L + 1) * 12;
+  const int64_t Vl = V;
   const double *rv = r + int64_t(v) * 2 * (L + 1);
   double *zv = z + int64_t(v) * 2 * (L + 1);
   // forward: y_k = r_k - Lo_k S_{k-1}^{-1} y_{k-1}; keep w_k = S_k^{-1} y_k in z
   double w0 = 0, w1 = 0;
   for (int k = 0; k <= L; ++k) {
-    const double *Fk = F + k * 12;
+    const double *Fk = fac + int64_t(k) * 12 * Vl + v;
     double y0 = rv[2 * k], y1 = rv[2 * k + 1];
     if (k > 0) {
-      y0 -= Fk[4] * w0 + Fk[5] * w1;
-      y1 -= Fk[6] * w0 + Fk[7] * w1;
+      y0 -= Fk[4 * Vl] * w0 + Fk[5 * Vl] * w1;
+      y1 -= Fk[6 * Vl] * w0 + Fk[7 * Vl] * w1;
     }
-    w0 = Fk[0] * y0 + Fk[1] * y1;
-    w1 = Fk[2] * y0 + Fk[3] * y1;
+    w0 = Fk[0] * y0 + Fk[Vl] * y1;
+    w1 = Fk[2 * Vl] * y0 + Fk[3 * Vl] * y1;
     zv[2 * k] = w0;
     zv[2 * k + 1] = w1;
   }
   // backward: z_k = w_k - S_k^{-1} Up_k z_{k+1}
   double z0 = zv[2 * L], z1 = zv[2 * L + 1];
   for (int k = L - 1; k >= 0; --k) {
-    const double *Fk = F + k * 12;
-    const double t0 = Fk[8] * z0 + Fk[9] * z1, t1 = Fk[10] * z0 + Fk[11] * z1;
-    z0 = zv[2 * k] - (Fk[0] * t0 + Fk[1] * t1);
-    z1 = zv[2 * k + 1] - (Fk[2] * t0 + Fk[3] * t1);
+    const double *Fk = fac + int64_t(k) * 12 * Vl + v;
+    const double t0 = Fk[8 * Vl] * z0 + Fk[9 * Vl] * z1, t1 = Fk[10 * Vl] * z0 + Fk[11 * Vl] * z1;
+    z0 = zv[2 * k] - (Fk[0] * t0 + Fk[Vl] * t1);
+    z1 = zv[2 * k + 1] - (Fk[2 * Vl] * t0 + Fk[3 * Vl] * t1);
     zv[2 * k] = z0;
     zv[2 * k + 1] = z1;
   }
@@ -127,25 +142,44 @@ __global__ __launch_bounds__(128) void colblock_apply_kernel(int V, int L, const
 
 constexpr int RED_BLOCK = 256;
 
-// partial[b * (nv + 1) + i] = sum over block b's rows of V_i . w (i < nv), and w . w (i = nv)
+constexpr int MD_GROUP = 8;   // dot products per pass over a block's chunk
+
+// partial[b * (nv + 1) + i] = sum over block b's rows of V_i . w (i < nv), and w . w (i = nv).
+// Vectors are taken MD_GROUP at a time, so each pass loads w once for all of them and has
+// MD_GROUP independent loads in flight per element; the summation order is fixed.
 __global__ __launch_bounds__(RED_BLOCK) void multidot_kernel(int64_t n, const double *__restrict__ V, int64_t ld,
                                                              int nv, const double *__restrict__ w,
                                                              double *__restrict__ partial) {
-  __shared__ double red[RED_BLOCK / 64];
+  __shared__ double red[MD_GROUP][RED_BLOCK / 64];
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t beg = int64_t(blockIdx.x) * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
-  for (int i = 0; i <= nv; ++i) {
-    const double *a = (i < nv) ? V + int64_t(i) * ld : w;
-    double s = 0.0;
-    for (int64_t p = beg + threadIdx.x; p < end; p += RED_BLOCK) s += a[p] * w[p];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  for (int i0 = 0; i0 <= nv; i0 += MD_GROUP) {
+    const int g = nv + 1 - i0 < MD_GROUP ? nv + 1 - i0 : MD_GROUP;
+    double s[MD_GROUP];
+#pragma unroll
+    for (int q = 0; q < MD_GROUP; ++q) s[q] = 0.0;
+    for (int64_t p = beg + threadIdx.x; p < end; p += RED_BLOCK) {
+      const double wp = w[p];
+#pragma unroll
+      for (int q = 0; q < MD_GROUP; ++q) {
+        if (q < g) {
+          const int i = i0 + q;
+          s[q] = fma(i < nv ? V[int64_t(i) * ld + p] : wp, wp, s[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < MD_GROUP; ++q) {
+      double t = s[q];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+      if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = t;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < g) {
       double t = 0.0;
-      for (int q = 0; q < RED_BLOCK / 64; ++q) t += red[q];
-      partial[int64_t(blockIdx.x) * (nv + 1) + i] = t;
+      for (int q = 0; q < RED_BLOCK / 64; ++q) t += red[threadIdx.x][q];
+      partial[int64_t(blockIdx.x) * (nv + 1) + i0 + threadIdx.x] = t;
     }
     __syncthreads();
   }
@@ -204,7 +238,7 @@ unsigned grid_for(int64_t n, int block) {
 }  // namespace
 
 fo_status spmv(const fo_mesh *mesh, const void *vals, int dtype, const double *x, double *y, hipStream_t s) {
-  const int64_t n = mesh->view.n_dofs;
+  const int64_t n = mesh->view.n_dofs / 2;   // nodes
   const int64_t threads = n * SPMV_LANES;
   const unsigned blocks = unsigned((threads + 255) / 256);
   if (dtype == FO_F32)
@@ -240,7 +274,7 @@ fo_status colblock_apply(const fo_mesh *mesh, const double *fac, const double *r
 
 int multidot_blocks(int64_t n) {
   const int64_t g = (n + 4 * RED_BLOCK - 1) / (4 * RED_BLOCK);
-  return int(g < 512 ? (g > 0 ? g : 1) : 512);
+  return int(g < 2048 ? (g > 0 ? g : 1) : 2048);
 }
 
 fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double *w, double *partial,
