@@ -223,6 +223,23 @@ def main():
     alg = algorithmic_bytes(m, M.nnz, jb)
     achieved = alg / kern_avg_s / 1e9
     traffic = measured_traffic() if args.jdtype == "f64" else None
+    # after the timed steps: the median of per-step times and 100 consecutive R+J
+    # evaluations (the paper's fill timing repeats the evaluation 100 times)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record()
+    for i in range(args.steps):
+        M.jacobian(Ud, dtype=args.jdtype, R=R, Jvals=J)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    median_ms = per_step[len(per_step) // 2] if len(per_step) % 2 else 0.5 * (
+        per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2])
+    ev0.record()
+    for _ in range(100):
+        M.jacobian(Ud, dtype=args.jdtype, R=R, Jvals=J)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_100 = ev0.elapsed_time(ev1)
     print(f"[bench] {ms_step:.3f} ms/step, assembly kernel {kern_avg_s * 1e3:.3f} ms, "
           f"{achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
 
@@ -245,6 +262,7 @@ def main():
             "cells": M.n_cells, "base_triangles": int(m.n_base_cells), "dofs": M.n_dofs,
             "nnz": M.nnz, "jacobian_values": args.jdtype,
         },
+        "timing": {"median_step_ms": median_ms, "consecutive_100_ms": ms_100},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

@@ -18,7 +18,7 @@ namespace {
 __device__ __forceinline__ int nlev(int k, int L) { return (k == 0 || k == L) ? 2 : 3; }
 __device__ __forceinline__ int cumlev(int k) { return k == 0 ? 0 : 3 * k - 1; }
 
-constexpr int SPMV_LANES = 8;   // lanes per node (pair of CSR rows)
+constexpr int SPMV_LANES = 16;   // lanes per node (pair of CSR rows)
 
 // The two rows of a node (components u and v) have the same column list (the pattern
 // couples full 2x2 dof blocks), and the second row follows the first in the CSR arrays:
