@@ -49,3 +49,13 @@ def test_status_strings_and_null_checks_without_gpu():
     assert L.fo_mesh_info(None, None, None, None, None) == _lib.FO_EINVAL
     assert L.fo_assemble_residual(None, None, None, None) == _lib.FO_EINVAL
     assert L.fo_assemble_jacobian(None, None, None, None, 0, 0, None) == _lib.FO_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for more exits with status 2 and says why."""
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
