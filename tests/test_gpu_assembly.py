@@ -184,3 +184,13 @@ def test_icesheet_full_size_sampled_rows():
             q = rowptr[jj] + np.searchsorted(cj, i)
             assert colidx[q] == i
             assert abs(Jv[p] - Jv[q]) <= 1e-12 * max(abs(Jv[p]), abs(Jv[rowptr[i]:rowptr[i + 1]]).max())
+    # the FP32 Jacobian in the same launch configuration, on the same sampled rows
+    R32, J32 = M.jacobian(Ud, dtype="f32")
+    torch.cuda.synchronize()
+    R32 = R32.cpu().numpy()
+    J32 = J32.cpu().numpy().astype(np.float64)
+    for n, i in enumerate(sel):
+        cols = colidx[rowptr[i]:rowptr[i + 1]]
+        ref = J_o[n].toarray().ravel()
+        assert np.max(np.abs(J32[rowptr[i]:rowptr[i + 1]] - ref[cols])) <= TOL32 * js[i], i
+        assert abs(R32[i] - r_o[n]) <= TOL64 * rs[i], i
