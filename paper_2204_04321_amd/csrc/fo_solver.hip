@@ -114,27 +114,51 @@ __global__ __launch_bounds__(128) void colblock_apply_kernel(int V, int L, const
   const int64_t Vl = V;
   const double *rv = r + int64_t(v) * 2 * (L + 1);
   double *zv = z + int64_t(v) * 2 * (L + 1);
-  // forward: y_k = r_k - Lo_k S_{k-1}^{-1} y_{k-1}; keep w_k = S_k^{-1} y_k in z
+  // forward: y_k = r_k - Lo_k S_{k-1}^{-1} y_{k-1}; keep w_k = S_k^{-1} y_k in z.  The
+  // next level's factors and right-hand side are loaded one level ahead.
+  double f[8], fn[8], rn0 = rv[0], rn1 = rv[1];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) fn[i] = fac[int64_t(i) * Vl + v];
   double w0 = 0, w1 = 0;
   for (int k = 0; k <= L; ++k) {
-    const double *Fk = fac + int64_t(k) * 12 * Vl + v;
-    double y0 = rv[2 * k], y1 = rv[2 * k + 1];
-    if (k > 0) {
-      y0 -= Fk[4 * Vl] * w0 + Fk[5 * Vl] * w1;
-      y1 -= Fk[6 * Vl] * w0 + Fk[7 * Vl] * w1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = fn[i];
+    double y0 = rn0, y1 = rn1;
+    if (k < L) {
+      const double *Fn = fac + int64_t(k + 1) * 12 * Vl + v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) fn[i] = Fn[i * Vl];
+      rn0 = rv[2 * k + 2];
+      rn1 = rv[2 * k + 3];
     }
-    w0 = Fk[0] * y0 + Fk[Vl] * y1;
-    w1 = Fk[2 * Vl] * y0 + Fk[3 * Vl] * y1;
+    if (k > 0) {
+      y0 -= f[4] * w0 + f[5] * w1;
+      y1 -= f[6] * w0 + f[7] * w1;
+    }
+    w0 = f[0] * y0 + f[1] * y1;
+    w1 = f[2] * y0 + f[3] * y1;
     zv[2 * k] = w0;
     zv[2 * k + 1] = w1;
   }
   // backward: z_k = w_k - S_k^{-1} Up_k z_{k+1}
   double z0 = zv[2 * L], z1 = zv[2 * L + 1];
+  double g[8], gn[8];
+  {
+    const double *Fk = fac + int64_t(L - 1 >= 0 ? L - 1 : 0) * 12 * Vl + v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { gn[i] = Fk[i * Vl]; gn[4 + i] = Fk[(8 + i) * Vl]; }
+  }
   for (int k = L - 1; k >= 0; --k) {
-    const double *Fk = fac + int64_t(k) * 12 * Vl + v;
-    const double t0 = Fk[8 * Vl] * z0 + Fk[9 * Vl] * z1, t1 = Fk[10 * Vl] * z0 + Fk[11 * Vl] * z1;
-    z0 = zv[2 * k] - (Fk[0] * t0 + Fk[Vl] * t1);
-    z1 = zv[2 * k + 1] - (Fk[2 * Vl] * t0 + Fk[3 * Vl] * t1);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) g[i] = gn[i];
+    if (k > 0) {
+      const double *Fn = fac + int64_t(k - 1) * 12 * Vl + v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { gn[i] = Fn[i * Vl]; gn[4 + i] = Fn[(8 + i) * Vl]; }
+    }
+    const double t0 = g[4] * z0 + g[5] * z1, t1 = g[6] * z0 + g[7] * z1;
+    z0 = zv[2 * k] - (g[0] * t0 + g[1] * t1);
+    z1 = zv[2 * k + 1] - (g[2] * t0 + g[3] * t1);
     zv[2 * k] = z0;
     zv[2 * k + 1] = z1;
   }
@@ -142,24 +166,24 @@ __global__ __launch_bounds__(128) void colblock_apply_kernel(int V, int L, const
 
 constexpr int RED_BLOCK = 256;
 
-constexpr int MD_GROUP = 8;   // dot products per pass over a block's chunk
+constexpr int MD_GROUP = 16;   // dot products per pass over a block's chunk
 
 // partial[b * (nv + 1) + i] = sum over block b's rows of V_i . w (i < nv), and w . w (i = nv).
 // Vectors are taken MD_GROUP at a time, so each pass loads w once for all of them and has
-// MD_GROUP independent loads in flight per element; the summation order is fixed.
+// MD_GROUP independent loads in flight per element.  Blocks stride through the vectors
+// together (grid-stride), so at any time the grid reads one window of each vector (DRAM
+// page locality); the summation order is fixed.
 __global__ __launch_bounds__(RED_BLOCK) void multidot_kernel(int64_t n, const double *__restrict__ V, int64_t ld,
                                                              int nv, const double *__restrict__ w,
                                                              double *__restrict__ partial) {
   __shared__ double red[MD_GROUP][RED_BLOCK / 64];
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t beg = int64_t(blockIdx.x) * chunk;
-  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  const int64_t stride = int64_t(gridDim.x) * RED_BLOCK;
   for (int i0 = 0; i0 <= nv; i0 += MD_GROUP) {
     const int g = nv + 1 - i0 < MD_GROUP ? nv + 1 - i0 : MD_GROUP;
     double s[MD_GROUP];
 #pragma unroll
     for (int q = 0; q < MD_GROUP; ++q) s[q] = 0.0;
-    for (int64_t p = beg + threadIdx.x; p < end; p += RED_BLOCK) {
+    for (int64_t p = int64_t(blockIdx.x) * RED_BLOCK + threadIdx.x; p < n; p += stride) {
       const double wp = w[p];
 #pragma unroll
       for (int q = 0; q < MD_GROUP; ++q) {
