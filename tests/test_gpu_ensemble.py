@@ -7,7 +7,7 @@ import torch
 from fo_inputs import ensemble_member
 from oracle import fo_oracle as fo
 
-from gpu_util import gpu_mesh, row_scaled_errors, to_dev
+from gpu_util import gpu_jacobian, gpu_mesh, row_scaled_errors, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -69,3 +69,29 @@ def test_ensemble_member_vs_oracle(members, k):
     er, ej = row_scaled_errors(Rs[k].cpu().numpy(), Jg, Ro, Jo, rs, js)
     assert er <= 1e-12 and ej <= 1e-12
     assert m.A != members[0][0].A or k == 0     # members carry their own rate factor
+
+
+def test_hexahedral_ensemble_equals_single_mesh():
+    """Hexahedral members (uneven sizes and layer counts) through the same persistent launch."""
+    from test_gpu_assembly import _box
+    from paper_2204_04321_amd.api import Ensemble
+    hex_members = [_box(nx, ny, L, "hex", 40 + i) for i, (nx, ny, L) in enumerate([(3, 2, 1), (9, 7, 4), (20, 13, 6)])]
+    Ms = [gpu_mesh(m) for m, _ in hex_members]
+    E = Ensemble(Ms)
+    Us = [to_dev(U) for _, U in hex_members]
+    for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        Rs = [torch.full((M.n_dofs,), float("nan"), dtype=torch.float64, device="cuda") for M in Ms]
+        Js = [torch.full((M.nnz,), float("nan"), dtype=tdt, device="cuda") for M in Ms]
+        E.assemble(Us, Rs, Js, dtype=dtype)
+        torch.cuda.synchronize()
+        for M, Ud, R, J in zip(Ms, Us, Rs, Js):
+            R1, J1 = M.jacobian(Ud, dtype=dtype)
+            torch.cuda.synchronize()
+            assert torch.equal(R, R1) and torch.equal(J, J1)
+    # and the largest member against the oracle
+    (m, U), M = hex_members[-1], Ms[-1]
+    R1, J1 = gpu_jacobian(M, U)
+    Ro, Jo = fo.assemble(m, U)
+    rs, js = fo.abs_scales(m, U)
+    er, ej = row_scaled_errors(R1, J1, Ro, Jo, rs, js)
+    assert er <= 1e-12 and ej <= 1e-12
