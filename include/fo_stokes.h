@@ -75,7 +75,9 @@ typedef struct fo_mesh fo_mesh;
 /* Validate the description, build the column-major numbering, the Jacobian
  * pattern and per-column tables once (the paper's memoisation of
  * solution-independent data, Sec. 4.1) and upload them.  On FO_EDEGENERATE
- * nothing is allocated.  Synchronises `stream`. */
+ * nothing is allocated.  FO_EINVAL also if a base vertex lies in more than 64
+ * base cells or has more than 255 neighbours (one wave assembles a vertex
+ * column's rows).  Synchronises `stream`. */
 fo_status fo_mesh_create(const fo_mesh_desc *desc, void *stream, fo_mesh **out);
 void fo_mesh_destroy(fo_mesh *mesh);
 
@@ -97,8 +99,8 @@ fo_status fo_assemble_residual(const fo_mesh *mesh, const double *U_dev, double 
 
 /* Jacobian J = dF/dU (eq. linearsystem) by forward-mode AD over the element
  * dofs, values written into Jvals_dev [nnz] of type `dtype` (FO_F64: double,
- * FO_F32: float; FP32 values come from FP32 derivative lanes over an FP64
- * primal evaluation).  kind = FO_JAC_PICARD drops the viscosity-derivative
+ * FO_F32: float; with FO_F32 the per-cell derivatives are computed in FP32 over
+ * an FP64 primal evaluation, summed over cells in FP64 and rounded once).  kind = FO_JAC_PICARD drops the viscosity-derivative
  * term.  If R_dev is not NULL the FP64 residual is written too, from the same
  * pass.  Jvals and R are overwritten. */
 fo_status fo_assemble_jacobian(const fo_mesh *mesh, const double *U_dev, double *R_dev,
