@@ -28,6 +28,31 @@ def _ptr(t: torch.Tensor | None) -> int | None:
     return int(t.data_ptr())
 
 
+def mesh_desc(desc, keep: list) -> "_lib.MeshDesc":
+    """fo_mesh_desc for `desc` (fields elem 'wedge' or 'hex', xy [V,2], cells [T,3|4],
+    surface, thickness, beta [V], sigma [L+1], constants A, n, rho, g, eps0).  The host
+    arrays it points to are appended to `keep`, which must outlive fo_mesh_create."""
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    d = _lib.MeshDesc()
+    d.elem = FO_WEDGE6 if desc.elem == "wedge" else FO_HEX8
+    d.n_base_verts = int(desc.xy.shape[0])
+    d.n_base_cells = int(desc.cells.shape[0])
+    d.n_layers = int(len(desc.sigma) - 1)
+    d.base_xy = arr(desc.xy, np.float64)
+    d.base_cells = arr(desc.cells, np.int32)
+    d.surface = arr(desc.surface, np.float64)
+    d.thickness = arr(desc.thickness, np.float64)
+    d.beta = arr(desc.beta, np.float64)
+    d.sigma = arr(desc.sigma, np.float64)
+    d.A, d.n, d.rho, d.g, d.eps0 = (float(desc.A), float(desc.n), float(desc.rho),
+                                     float(desc.g), float(desc.eps0))
+    return d
+
+
 class Mesh:
     """An uploaded extruded mesh.  `desc` is any object with the fields elem ('wedge' or
     'hex'), xy [V,2], cells [T,3|4], surface, thickness, beta [V], sigma [L+1], and the
@@ -36,26 +61,7 @@ class Mesh:
     def __init__(self, desc, stream=None):
         L = _lib.lib()
         self._keep = []
-
-        def arr(a, dt):
-            a = np.ascontiguousarray(a, dtype=dt)
-            self._keep.append(a)
-            return a.ctypes.data
-
-        elem = FO_WEDGE6 if desc.elem == "wedge" else FO_HEX8
-        d = _lib.MeshDesc()
-        d.elem = elem
-        d.n_base_verts = int(desc.xy.shape[0])
-        d.n_base_cells = int(desc.cells.shape[0])
-        d.n_layers = int(len(desc.sigma) - 1)
-        d.base_xy = arr(desc.xy, np.float64)
-        d.base_cells = arr(desc.cells, np.int32)
-        d.surface = arr(desc.surface, np.float64)
-        d.thickness = arr(desc.thickness, np.float64)
-        d.beta = arr(desc.beta, np.float64)
-        d.sigma = arr(desc.sigma, np.float64)
-        d.A, d.n, d.rho, d.g, d.eps0 = (float(desc.A), float(desc.n), float(desc.rho),
-                                         float(desc.g), float(desc.eps0))
+        d = mesh_desc(desc, self._keep)
         h = C.c_void_p()
         check(L.fo_mesh_create(C.byref(d), _stream(stream), C.byref(h)))
         self._keep = []

@@ -59,3 +59,57 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def _bad_mesh_cases():
+    """(name, mesh, expected status, message fragment) for descriptors fo_mesh_create rejects
+    during host-side validation, before any device call."""
+    from dataclasses import replace
+
+    import numpy as np
+
+    from fo_inputs import structured_box
+    from fo_inputs.meshgen import ExtrudedMesh
+
+    xy, cells, sigma = structured_box(3, 2, 2, 3e3, 2e3, elem="wedge")
+    V = xy.shape[0]
+    good = ExtrudedMesh("wedge", xy, cells, np.full(V, 1000.0), np.full(V, 800.0), np.full(V, 500.0), sigma)
+    H0 = good.thickness.copy(); H0[3] = 0.0
+    bneg = good.beta.copy(); bneg[1] = -1.0
+    cw = good.cells.copy(); cw[0] = cw[0][::-1]
+    oob = good.cells.copy(); oob[2, 1] = V + 5
+    rep = good.cells.copy(); rep[1, 2] = rep[1, 0]
+    # a fan of 70 triangles around one vertex: more than 64 cells at a vertex
+    ang = np.linspace(0, 2 * np.pi, 71)[:-1]
+    fxy = np.vstack([[0.0, 0.0], np.stack([1e3 * np.cos(ang), 1e3 * np.sin(ang)], 1)])
+    fcells = np.array([[0, 1 + i, 1 + (i + 1) % 70] for i in range(70)], dtype=np.int32)
+    nf = fxy.shape[0]
+    fan = ExtrudedMesh("wedge", fxy, fcells, np.full(nf, 1000.0), np.full(nf, 800.0), np.full(nf, 500.0),
+                       np.linspace(0, 1, 3))
+    return [
+        ("zero thickness", replace(good, thickness=H0), -4, b"thickness"),
+        ("negative beta", replace(good, beta=bneg), -4, b"beta"),
+        ("clockwise cell", replace(good, cells=cw), -4, b"counter-clockwise"),
+        ("vertex id out of range", replace(good, cells=oob), -1, b"out of range"),
+        ("repeated vertex", replace(good, cells=rep), -4, b"repeated vertex"),
+        ("sigma not increasing", replace(good, sigma=np.array([0.0, 0.6, 0.4, 1.0])), -4, b"sigma"),
+        ("sigma not ending at 1", replace(good, sigma=np.array([0.0, 0.5, 0.9])), -4, b"sigma"),
+        ("no layers", replace(good, sigma=np.array([0.0])), -1, b"L >= 1"),
+        ("non-positive A", replace(good, A=0.0), -1, b"constants"),
+        ("Glen exponent below 1", replace(good, n=0.5), -1, b"constants"),
+        ("more than 64 cells at a vertex", fan, -1, b"more than 64"),
+    ]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("case", _bad_mesh_cases(), ids=lambda c: c[0])
+def test_mesh_validation_rejects_without_gpu(case):
+    from paper_2204_04321_amd import _lib
+    from paper_2204_04321_amd.api import mesh_desc
+    name, m, status, frag = case
+    keep = []
+    d = mesh_desc(m, keep)
+    out = ctypes.c_void_p()
+    assert _lib.lib().fo_mesh_create(ctypes.byref(d), None, ctypes.byref(out)) == status, name
+    assert frag in _lib.lib().fo_last_error(), (name, _lib.lib().fo_last_error())
+    assert not out.value
