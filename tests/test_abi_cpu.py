@@ -113,3 +113,22 @@ def test_mesh_validation_rejects_without_gpu(case):
     assert _lib.lib().fo_mesh_create(ctypes.byref(d), None, ctypes.byref(out)) == status, name
     assert frag in _lib.lib().fo_last_error(), (name, _lib.lib().fo_last_error())
     assert not out.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_plain_c_caller(tmp_path):
+    """The ABI is usable from C: compile the example against the header, link the library,
+    run the host-side calls."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "abi_check")
+    src = os.path.join(ROOT, "paper_2204_04321_amd", "examples", "abi_check.c")
+    libdir = os.path.dirname(LIB)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), src, "-o", exe,
+                    "-L", libdir, "-lfo_stokes", "-Wl,-rpath," + libdir], check=True, capture_output=True)
+    p = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert p.returncode == 0, p.stdout + p.stderr
+    assert "degenerate" in p.stdout
