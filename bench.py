@@ -3,12 +3,16 @@
 ice-sheet-scale wedge mesh (Delaunay of 125k seeded points in a 1500 x 700 km ellipse,
 10 layers: ~2.49M wedges, 2.75M dofs), one GPU.
 
-A step is one fo_assemble_jacobian call (zero fills + one assembly kernel writing the FP64
-residual and the FP64 CSR Jacobian values) with all inputs resident in HBM.  Prints one
-JSON line with cells/s, the roofline position of the assembly kernel (algorithmic bytes
-over its HIP-event-timed duration) and the FP64 CPU oracle timed on a bounded sample.
+A step is one fo_assemble_jacobian call (one assembly kernel writing the FP64 residual and
+the FP64 CSR Jacobian values; no zero fill is needed) with all inputs resident in HBM.
+Prints one JSON line with cells/s, the roofline position of the assembly kernel
+(algorithmic bytes over its HIP-event-timed duration, and algorithmic flops against the
+FP64 vector peak), the measured HBM traffic when the committed counter figures match the
+kernel source, and the FP64 CPU oracle timed on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu] [--jdtype f64|f32]
+    python bench.py --workload ensemble     # 64-member batch in one persistent launch
+    python bench.py --workload newton       # Newton solves, FP64 and FP32 Jacobian values
 """
 from __future__ import annotations
 
