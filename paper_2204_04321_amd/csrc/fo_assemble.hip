@@ -598,22 +598,20 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     auto flush = [&](int lev_k, int slot) {
       const int nl = nlev(lev_k, L);
       const int lk = cumlev(lev_k);
-      const double *wsrc = Jw + slot * max_slot;
-      double *wdst = Jw + slot * max_slot;
+      double *wb = Jw + slot * max_slot;   // 16-byte aligned, as is every column's slot
       for (int i0 = 0; i0 < nvt; i0 += 4) {
         if constexpr (JAC) {
-          double val[4][3];
+          // each lane moves two consecutive entries: one 16-byte LDS read and one 16-byte
+          // clearing write per column cover up to 128 entries (degree <= 10 at nl = 3)
+          double2 val[4];
           int nn[4], so[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int ii = i0 + i < nvt ? i0 + i : nvt - 1;
             so[i] = __builtin_amdgcn_readlane(my_soff, ii);
             nn[i] = i0 + i < nvt ? 4 * nl * __builtin_amdgcn_readlane(my_deg, ii) : 0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const int e = lane + c * WAVE;
-              val[i][c] = wsrc[so[i] + (e < nn[i] ? e : 0)];
-            }
+            const int e = 2 * lane;
+            val[i] = *reinterpret_cast<const double2 *>(wb + so[i] + (e < nn[i] ? e : 0));
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -623,13 +621,19 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
             const int64_t col = int64_t(unsigned(__builtin_amdgcn_readlane(my_col_lo, ii))) |
                                 (int64_t(__builtin_amdgcn_readlane(my_col_hi, ii)) << 32);
             JT *dst = J + col + int64_t(4) * D * lk;
-            double *src = wdst + so[i];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const int e = lane + c * WAVE;
-              if (e < nn[i]) { dst[e] = JT(val[i][c]); src[e] = 0.0; }
+            double *src = wb + so[i];
+            const int e = 2 * lane;   // nn is a multiple of 4, so e < nn implies e + 1 < nn
+            if (e < nn[i]) {
+              dst[e] = JT(val[i].x);
+              dst[e + 1] = JT(val[i].y);
+              *reinterpret_cast<double2 *>(src + e) = make_double2(0.0, 0.0);
             }
-            for (int e = lane + 3 * WAVE; e < nn[i]; e += WAVE) { dst[e] = JT(src[e]); src[e] = 0.0; }
+            for (int f = e + 2 * WAVE; f < nn[i]; f += 2 * WAVE) {
+              const double2 w = *reinterpret_cast<const double2 *>(src + f);
+              dst[f] = JT(w.x);
+              dst[f + 1] = JT(w.y);
+              *reinterpret_cast<double2 *>(src + f) = make_double2(0.0, 0.0);
+            }
           }
         }
         if (lane < 8 && i0 + (lane >> 1) < nvt) {
