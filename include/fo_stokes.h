@@ -74,8 +74,9 @@ typedef struct fo_mesh fo_mesh;
 
 /* Validate the description, build the column-major numbering, the Jacobian
  * pattern and per-column tables once (the paper's memoisation of
- * solution-independent data, Sec. 4.1) and upload them.  On FO_EDEGENERATE
- * nothing is allocated.  FO_EINVAL also if a base vertex lies in more than 64
+ * solution-independent data, Sec. 4.1) and upload them.  FO_EDEGENERATE also
+ * if a base vertex lies in no base cell.  On FO_EDEGENERATE nothing is
+ * allocated.  FO_EINVAL also if a base vertex lies in more than 64
  * base cells or has more than 255 neighbours (one wave assembles a vertex
  * column's rows).  Synchronises `stream`. */
 fo_status fo_mesh_create(const fo_mesh_desc *desc, void *stream, fo_mesh **out);

@@ -165,7 +165,6 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   // scatter pattern saturate the LDS data path (measured), FP64 ones do not.
   double *Jw = reinterpret_cast<double *>(smem);                                               // [2][max_slot]
   double *Rw = reinterpret_cast<double *>(smem + (JAC ? 2 * size_t(max_slot) * sizeof(double) : 0));  // [2][2 max_tv]
-
   const int lane = threadIdx.x;
   const int vb = task.y, ve = task.z, ib = task.w;
   const int ie = m.vc_ptr[ve];
@@ -177,8 +176,16 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   const int al = act ? m.vc_pos[item] : 0;
   const int Dv = m.deg[v];
   const int soff = m.slot_off[v];
-  const int rloc = 2 * (v - vb);
+  // per-item integers fixed over the layers, packed: slot offset (12 bits, < 2048), degree
+  // (8), column position in the task (6, a task has at most 64 columns), corner (2).  Each
+  // layer re-derives them, the corner ranks and the corners' addresses from this word, the
+  // rank word and the vertex ids, passed through an empty asm statement: otherwise the
+  // compiler hoists the derived addresses out of the layer loop and spills them, and every
+  // reload costs a scratch round trip that serialises the layer's gather loads.
+  const uint32_t imeta = uint32_t(soff) | (uint32_t(Dv) << 12) | (uint32_t(v - vb) << 20) | (uint32_t(al) << 26);
   const int slot_size = m.slot_off[ve - 1] + 12 * m.deg[ve - 1];
+  // 8 bits per corner: its rank in v's neighbour list
+  const uint32_t irank = act ? m.item_rank[item] : 0u;
 
   // ---- per-item constants -----------------------------------------------------------------
   int vid[NV];
@@ -234,22 +241,79 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     for (int e = lane; e < slot_size; e += WAVE) { Jw[e] = 0.0; Jw[max_slot + e] = 0.0; }
   }
   for (int e = lane; e < 2 * (ve - vb); e += WAVE) { Rw[e] = 0.0; Rw[2 * max_tv + e] = 0.0; }
-
   wave_sync();
+
+  // ---- bed friction on the lower face of the bottom layer: rows of v's level-0 node, added
+  // to the level-0 windows before the layer loop ----------------------------------------------
+  if (act) {
+    double bx_[NV], by_[NV], bb_[NV], bH_[NV], bs_[NV], be[NV], zb[NV], ub[NV], vb_[NV];
+    load_geo(bx_, by_, bb_, bH_, bs_);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      be[i] = m.sb[vid[i]].y;
+      zb[i] = bb_[i] + m.sigma[0] * bH_[i];
+      const double2 a0 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1)));
+      ub[i] = a0.x; vb_[i] = a0.y;
+    }
+    double Rf0 = 0, Rf1 = 0;
+    AT Jf[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) Jf[j] = AT(0);
+#pragma unroll
+    for (int r = 0; r < NQB; ++r) {
+      double txx = 0, txy = 0, txz = 0, tyx = 0, tyy = 0, tyz = 0, br = 0, ur = 0, vr = 0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const double dx = Q.bdlx[r][i], dy = Q.bdly[r][i], lm = Q.blam[r][i];
+        txx += bx_[i] * dx; txy += by_[i] * dx; txz += zb[i] * dx;
+        tyx += bx_[i] * dy; tyy += by_[i] * dy; tyz += zb[i] * dy;
+        br += be[i] * lm; ur += ub[i] * lm; vr += vb_[i] * lm;
+      }
+      const double nx = txy * tyz - txz * tyy, ny = txz * tyx - txx * tyz, nz = txx * tyy - txy * tyx;
+      const double wb = Q.bw[r] * sqrt(nx * nx + ny * ny + nz * nz) * br;
+      const double la = sel4(al, Q.blam[r][0], Q.blam[r][1], Q.blam[r][2], Q.blam[r][NV - 1]);
+      Rf0 += wb * ur * la;
+      Rf1 += wb * vr * la;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) Jf[j] += AT(wb * la * Q.blam[r][j]);
+    }
+    const int rl0 = 2 * (v - vb);
+    lds_add(Rw + rl0, Rf0);
+    lds_add(Rw + rl0 + 1, Rf1);
+    if constexpr (JAC) {
+      // row (v, 0, c), column (corner j, level 0, component c)
+      const int nl0 = nlev(0, L);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+          lds_add(Jw + soff + c * 2 * nl0 * Dv + int((irank >> (8 * j)) & 255u) * 2 * nl0 + c, double(Jf[j]));
+    }
+  }
 
   for (int k = 0; k < L; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
-    // gather levels k and k+1 (repeat loads hit the cache; nothing is carried between
-    // layers so the quadrature loop keeps few registers live)
+    uint32_t ipy = irank, imt = imeta;
+    int vidk[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) vidk[i] = vid[i];
+    // one statement, so that reloads of spilled operands are issued together
+    if constexpr (NV == 3)
+      asm volatile("" : "+v"(ipy), "+v"(imt), "+v"(vidk[0]), "+v"(vidk[1]), "+v"(vidk[2]));
+    else
+      asm volatile("" : "+v"(ipy), "+v"(imt), "+v"(vidk[0]), "+v"(vidk[1]), "+v"(vidk[2]), "+v"(vidk[NV - 1]));
+    const int al = int(imt >> 26), soff = int(imt & 4095u), Dv = int((imt >> 12) & 255u);
+    const int rloc = 2 * int((imt >> 20) & 63u);
+    // gather levels k and k+1 (repeat loads hit the cache)
     double zlo[NV], ulo[NV], vlo[NV], dz[NV], du[NV], dv[NV];
     const double s0 = m.sigma[k], s1 = m.sigma[k + 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const double4 g = m.geo[vid[i]];
+      const double4 g = m.geo[vidk[i]];
       zlo[i] = g.z + s0 * g.w;
       dz[i] = (g.z + s1 * g.w) - zlo[i];
-      const double2 a0 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1) + k));
-      const double2 a1 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1) + k + 1));
+      const double2 a0 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vidk[i]) * (L + 1) + k));
+      const double2 a1 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vidk[i]) * (L + 1) + k + 1));
       ulo[i] = a0.x; vlo[i] = a0.y;
       du[i] = a1.x - a0.x;
       dv[i] = a1.y - a0.y;
@@ -526,43 +590,6 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   
     }
 
-    // ---- bed friction on the lower face of the bottom layer (uniform branch) -------------
-    if (k == 0) {
-      double bx_[NV], by_[NV], bb_[NV], bH_[NV], bs_[NV], be[NV], zb[NV], ub[NV], vb_[NV];
-      load_geo(bx_, by_, bb_, bH_, bs_);
-#pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        be[i] = m.sb[vid[i]].y;
-        zb[i] = bb_[i] + m.sigma[0] * bH_[i];
-        const double2 a0 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vid[i]) * (L + 1)));
-        ub[i] = a0.x; vb_[i] = a0.y;
-      }
-#pragma unroll
-      for (int r = 0; r < NQB; ++r) {
-        double txx = 0, txy = 0, txz = 0, tyx = 0, tyy = 0, tyz = 0, br = 0, ur = 0, vr = 0;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-          const double dx = Q.bdlx[r][i], dy = Q.bdly[r][i], lm = Q.blam[r][i];
-          txx += bx_[i] * dx; txy += by_[i] * dx; txz += zb[i] * dx;
-          tyx += bx_[i] * dy; tyy += by_[i] * dy; tyz += zb[i] * dy;
-          br += be[i] * lm; ur += ub[i] * lm; vr += vb_[i] * lm;
-        }
-        const double nx = txy * tyz - txz * tyy, ny = txz * tyx - txx * tyz, nz = txx * tyy - txy * tyx;
-        const double wb = Q.bw[r] * sqrt(nx * nx + ny * ny + nz * nz) * br;
-        const double la = sel4(al, Q.blam[r][0], Q.blam[r][1], Q.blam[r][2], Q.blam[r][NV - 1]);
-        Rb0 += wb * ur * la;
-        Rb1 += wb * vr * la;
-        if constexpr (JAC) {
-#pragma unroll
-          for (int j = 0; j < NV; ++j) {
-            const AT f = AT(wb * la * Q.blam[r][j]);
-            Jx[0][0][0][j][0] += f;
-            Jx[0][1][1][j][0] += f;
-          }
-        }
-      }
-    }
-
     // ---- add v's rows into the level windows ------------------------------------------------
     if (act) {
       double *Rcur = Rw + cur * 2 * max_tv, *Rnxt = Rw + nxt * 2 * max_tv;
@@ -573,7 +600,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
       if constexpr (JAC) {
         int rk[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) rk[i] = m.rank[(int64_t(t) * NV + al) * NV + i];
+        for (int i = 0; i < NV; ++i) rk[i] = int((ipy >> (8 * i)) & 255u);
         const int nlk = nlev(k, L), nl1 = nlev(k + 1, L);
         const int offk = k > 0 ? 1 : 0;     // level k sits at window position 1 unless k = 0
         double *Wk = Jw + cur * max_slot + soff, *Wk1 = Jw + nxt * max_slot + soff;
@@ -702,11 +729,15 @@ fo_status ensure_tables(int device) {
   return FO_OK;
 }
 
+// LDS of one task: two level windows (Jacobian) and two residual windows
+size_t window_bytes(bool jac, int max_slot, int max_tv) {
+  return (jac ? 2 * size_t(max_slot) * sizeof(double) : 0) + 2 * 2 * size_t(max_tv) * sizeof(double);
+}
+
 template <int NV, bool JAC, class JT, bool N3>
 fo_status launch_t(const fo_mesh *mesh, const double *U, double *R, JT *J, int kind, hipStream_t s) {
   const MeshView &m = mesh->view;
-  const size_t lds = (JAC ? 2 * size_t(mesh->max_slot) * sizeof(double) : 0) +
-                     2 * 2 * size_t(mesh->max_task_verts) * sizeof(double);
+  const size_t lds = window_bytes(JAC, mesh->max_slot, mesh->max_task_verts);
   fo_status st = profile_begin(mesh, s);
   if (st != FO_OK) return st;
   hipLaunchKernelGGL((owner_kernel<NV, JAC, JT, N3>), dim3(unsigned(mesh->n_tasks)), dim3(WAVE), lds, s, m,
@@ -724,7 +755,7 @@ fo_status launch_n(const fo_mesh *mesh, const double *U, double *R, JT *J, int k
 
 template <int NV, bool JAC, class JT, bool N3>
 fo_status launch_ens_t(const EnsembleLaunch &E, int kind, hipStream_t s) {
-  const size_t lds = (JAC ? 2 * size_t(E.max_slot) * sizeof(double) : 0) + 2 * 2 * size_t(E.max_tv) * sizeof(double);
+  const size_t lds = window_bytes(JAC, E.max_slot, E.max_tv);
   auto kern = ensemble_kernel<NV, JAC, JT, N3>;
   int per_cu = 0;
   FO_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVE, lds));

@@ -52,6 +52,8 @@ struct MeshView {
   const uint8_t *vc_pos;   // [T * nv]
   const int32_t *item_vtx; // [T * nv] vertex of each item
   const int32_t *slot_off; // [V] offset of v's rows inside its task's LDS level window
+  const uint32_t *item_rank; // [T * nv] per item, 8 bits per corner: its rank in the
+                             // item vertex's neighbour list
   double rho_g;            // rho * g
   double visc_pref;        // 1/2 A^(-1/n)
   double visc_exp;         // (1 - n) / (2 n)
@@ -82,6 +84,7 @@ struct fo_mesh {
   uint8_t *vc_pos = nullptr;
   int32_t *item_vtx = nullptr;
   int32_t *slot_off = nullptr;
+  uint32_t *item_rank = nullptr;
   int4 *tasks = nullptr;        // [n_tasks] {member, v_begin, v_end, item_begin}
   int32_t n_tasks = 0;
   std::vector<int4> tasks_host; // host copy, for building ensembles

@@ -70,7 +70,7 @@ static void free_mesh(fo_mesh *m) {
   release_events(m);
   void *ptrs[] = {m->geo, m->sb, m->colptr, m->deg, m->cells, m->rank, m->sigma,
                   m->nbr_ptr, m->nbr_idx, m->self_rank, m->vc_ptr, m->vc_idx, m->vc_pos,
-                  m->item_vtx, m->slot_off, m->tasks, m->rowptr, m->colidx};
+                  m->item_vtx, m->slot_off, m->item_rank, m->tasks, m->rowptr, m->colidx};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -212,6 +212,8 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
     for (int32_t v = 0; v < int32_t(V); ++v) {
       const int32_t ni = vc_ptr[v + 1] - vc_ptr[v];
       const int32_t sz = 12 * deg[v];
+      if (ni == 0)
+        return fail(FO_EDEGENERATE, "fo_mesh_create: vertex " + std::to_string(v) + " lies in no base cell");
       if (ni > kMaxItems || sz > kMaxSlot)
         return fail(FO_EINVAL, "fo_mesh_create: vertex " + std::to_string(v) + " lies in more than 64 base cells");
       if (v > vb && (items + ni > kMaxItems || slot + sz > kMaxSlot)) {
@@ -227,6 +229,15 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
     tasks.push_back(make_int4(0, vb, int32_t(V), vc_ptr[vb]));
     max_slot = std::max(max_slot, slot);
     max_tv = std::max(max_tv, int32_t(V) - vb);
+  }
+  // per item, the neighbour rank of each corner in the item vertex's list, 8 bits per corner
+  std::vector<uint32_t> item_rank(size_t(T) * nv);
+  for (int64_t p = 0; p < T * nv; ++p) {
+    const int64_t t = vc_idx[p];
+    const int a = vc_pos[p];
+    uint32_t rx = 0;
+    for (int b = 0; b < nv; ++b) rx |= uint32_t(rank[(t * nv + a) * nv + b]) << (8 * b);
+    item_rank[p] = rx;
   }
   std::vector<double4> geo(V);
   std::vector<double2> sb(V);
@@ -256,6 +267,7 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   UP(vc_pos, vc_pos);
   UP(item_vtx, item_vtx);
   UP(slot_off, slot_off);
+  UP(item_rank, item_rank);
   UP(tasks, tasks);
 #undef UP
   if ((st = dev_upload(&m->cells, C, size_t(T) * nv, s)) != FO_OK) { free_mesh(m); return st; }
@@ -281,6 +293,7 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   mv.vc_pos = m->vc_pos;
   mv.item_vtx = m->item_vtx;
   mv.slot_off = m->slot_off;
+  mv.item_rank = m->item_rank;
   m->n_tasks = int32_t(tasks.size());
   m->tasks_host = tasks;
   m->max_slot = max_slot;

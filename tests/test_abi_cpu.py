@@ -86,8 +86,12 @@ def _bad_mesh_cases():
     nf = fxy.shape[0]
     fan = ExtrudedMesh("wedge", fxy, fcells, np.full(nf, 1000.0), np.full(nf, 800.0), np.full(nf, 500.0),
                        np.linspace(0, 1, 3))
+    # an extra vertex that no cell uses
+    lone = replace(good, xy=np.vstack([good.xy, [[9e3, 9e3]]]), surface=np.append(good.surface, 1000.0),
+                   thickness=np.append(good.thickness, 800.0), beta=np.append(good.beta, 500.0))
     return [
         ("zero thickness", replace(good, thickness=H0), -4, b"thickness"),
+        ("vertex in no cell", lone, -4, b"no base cell"),
         ("negative beta", replace(good, beta=bneg), -4, b"beta"),
         ("clockwise cell", replace(good, cells=cw), -4, b"counter-clockwise"),
         ("vertex id out of range", replace(good, cells=oob), -1, b"out of range"),
