@@ -291,6 +291,19 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     }
   }
 
+  // FP32 tangents: the upper row's entries at the upper level of layer k are kept in
+  // registers and added together with layer k + 1's lower-row entries at the same places,
+  // a quarter fewer LDS adds.  The FP64 kernel has no registers to spare for them (spills
+  // made it slower), so it adds both.  [c][d][corner]
+  constexpr bool CARRY = JAC && sizeof(JT) == 4;
+  AT carry[2][2][NV];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) carry[c][d][j] = AT(0);
+
   for (int k = 0; k < L; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
     uint32_t ipy = irank, imt = imeta;
@@ -612,8 +625,11 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
             for (int lev = 0; lev < 2; ++lev)
 #pragma unroll
               for (int d = 0; d < 2; ++d) {
-                lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, double(Jx[0][c][d][j][lev]));
-                lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, double(Jx[1][c][d][j][lev]));
+                AT lo = Jx[0][c][d][j][lev];
+                if (CARRY && lev == 0) lo += carry[c][d][j];
+                lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, double(lo));
+                if (CARRY && lev == 1 && k + 1 < L) carry[c][d][j] = Jx[1][c][d][j][1];
+                else lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, double(Jx[1][c][d][j][lev]));
               }
       }
     }
