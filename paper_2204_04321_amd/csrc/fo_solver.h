@@ -8,10 +8,11 @@ fo_status spmv(const fo_mesh *mesh, const void *vals, int dtype, const double *x
 fo_status colblock_factor(const fo_mesh *mesh, const void *vals, int dtype, double *fac, hipStream_t s);
 fo_status colblock_apply(const fo_mesh *mesh, const double *fac, const double *r, double *z, hipStream_t s);
 int multidot_blocks(int64_t n);
-// out[0..nv-1] = V_i . w, out[nv] = w . w (partial: multidot_blocks(n) * (nv + 1) doubles)
+// out[0..nv-1] = V_i . w, out[nv] = w . w (partial: multidot_blocks(n) * (nv + 1) doubles;
+// n and ld even, FO_EINVAL otherwise)
 fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double *w, double *partial,
                    double *out, hipStream_t s);
-// w += sign * sum_i h_i V_i
+// w += sign * sum_i h_i V_i (n and ld even, FO_EINVAL otherwise)
 fo_status multiaxpy(int64_t n, const double *V, int64_t ld, int nv, const double *h, double *w, double sign,
                     hipStream_t s);
 fo_status axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);

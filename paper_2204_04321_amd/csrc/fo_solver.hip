@@ -1,4 +1,4 @@
-// Linear-algebra kernels behind fo_newton_solve: CSR SpMV with FP64 or FP32 values,
+// Linear-algebra kernels behind fo_newton_solve: SpMV over the Jacobian layout with FP64 or FP32 values,
 // the vertical-column block preconditioner, and the fused Krylov vector kernels.
 //
 // Preconditioner.  Each vertex column of the extruded mesh couples its own 2(L+1)
@@ -18,26 +18,45 @@ namespace {
 __device__ __forceinline__ int nlev(int k, int L) { return (k == 0 || k == L) ? 2 : 3; }
 __device__ __forceinline__ int cumlev(int k) { return k == 0 ? 0 : 3 * k - 1; }
 
-constexpr int SPMV_LANES = 16;   // lanes per node (pair of CSR rows)
+constexpr int SPMV_LANES = 8;   // lanes per node (pair of rows)
 
-// The two rows of a node (components u and v) have the same column list (the pattern
-// couples full 2x2 dof blocks), and the second row follows the first in the CSR arrays:
-// each lane group reads a column index and x entry once for both rows.
+template <class JT> struct Pair2;
+template <> struct Pair2<double> { using T = double2; };
+template <> struct Pair2<float> { using T = float2; };
+
+// y = J x over the Jacobian's own layout, without the CSR column indices.  The two rows of
+// node (v, k) (components u and v) share one column list and follow each other: the row
+// block starts at colptr[v] + 4 D cumlev(k), row c at + c 2 nl D, and entry (r, lev, d)
+// at + r 2 nl + 2 lev + d couples neighbour r of v (sorted list), level klo + lev,
+// component d.  Each lane takes whole (u, v) column pairs: one 16-byte x load and one
+// two-value load per row.
 template <class JT>
-__global__ __launch_bounds__(256) void spmv_kernel(int64_t n_nodes, const int64_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ colidx,
-                                                   const JT *__restrict__ vals,
-                                                   const double *__restrict__ x, double *__restrict__ y) {
+__global__ __launch_bounds__(256) void spmv_kernel(int V, int L, const int64_t *__restrict__ colptr,
+                                                   const int32_t *__restrict__ nbr_ptr,
+                                                   const int32_t *__restrict__ nbr_idx,
+                                                   const JT *__restrict__ vals, const double *__restrict__ x,
+                                                   double *__restrict__ y) {
+  using T2 = typename Pair2<JT>::T;
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t node = gid / SPMV_LANES;
   const int sub = int(gid % SPMV_LANES);
+  const int64_t n_nodes = int64_t(V) * (L + 1);
   double a0 = 0.0, a1 = 0.0;
   if (node < n_nodes) {
-    const int64_t b = rowptr[2 * node], len = rowptr[2 * node + 1] - b;
-    for (int64_t p = b + sub; p < b + len; p += SPMV_LANES) {
-      const double xv = x[colidx[p]];
-      a0 = fma(double(vals[p]), xv, a0);
-      a1 = fma(double(vals[p + len]), xv, a1);
+    const int v = int(node / (L + 1)), k = int(node - int64_t(v) * (L + 1));
+    const int nb = nbr_ptr[v], D = nbr_ptr[v + 1] - nb;
+    const int nl = nlev(k, L);
+    const int klo = k > 0 ? k - 1 : 0;
+    const JT *row = vals + colptr[v] + int64_t(4) * D * cumlev(k);
+    const int len = 2 * nl * D;
+    for (int q = sub; q < nl * D; q += SPMV_LANES) {
+      const int r = nl == 3 ? (q * 43691) >> 17 : q >> 1;   // q / nl, exact for q < 65536
+      const int lev = q - r * nl;
+      const int64_t col = 2 * (int64_t(nbr_idx[nb + r]) * (L + 1) + klo + lev);
+      const double2 xv = *reinterpret_cast<const double2 *>(x + col);
+      const T2 v0 = *reinterpret_cast<const T2 *>(row + 2 * q), v1 = *reinterpret_cast<const T2 *>(row + len + 2 * q);
+      a0 = fma(double(v0.x), xv.x, fma(double(v0.y), xv.y, a0));
+      a1 = fma(double(v1.x), xv.x, fma(double(v1.y), xv.y, a1));
     }
   }
 #pragma unroll
@@ -166,30 +185,33 @@ __global__ __launch_bounds__(128) void colblock_apply_kernel(int V, int L, const
 
 constexpr int RED_BLOCK = 256;
 
-constexpr int MD_GROUP = 16;   // dot products per pass over a block's chunk
+constexpr int MD_GROUP = 24;   // dot products per pass over a block's chunk
 
 // partial[b * (nv + 1) + i] = sum over block b's rows of V_i . w (i < nv), and w . w (i = nv).
 // Vectors are taken MD_GROUP at a time, so each pass loads w once for all of them and has
-// MD_GROUP independent loads in flight per element.  Blocks stride through the vectors
-// together (grid-stride), so at any time the grid reads one window of each vector (DRAM
-// page locality); the summation order is fixed.
-__global__ __launch_bounds__(RED_BLOCK) void multidot_kernel(int64_t n, const double *__restrict__ V, int64_t ld,
+// MD_GROUP independent loads in flight per element pair.  Each lane takes two consecutive
+// entries (16-byte loads; n and ld are even).  Blocks stride through the vectors together
+// (grid-stride), so at any time the grid reads one window of each vector (DRAM page
+// locality); the summation order is fixed.
+__global__ __launch_bounds__(RED_BLOCK) void multidot_kernel(int64_t n2, const double *__restrict__ V, int64_t ld,
                                                              int nv, const double *__restrict__ w,
                                                              double *__restrict__ partial) {
   __shared__ double red[MD_GROUP][RED_BLOCK / 64];
   const int64_t stride = int64_t(gridDim.x) * RED_BLOCK;
+  const double2 *w2 = reinterpret_cast<const double2 *>(w);
   for (int i0 = 0; i0 <= nv; i0 += MD_GROUP) {
     const int g = nv + 1 - i0 < MD_GROUP ? nv + 1 - i0 : MD_GROUP;
     double s[MD_GROUP];
 #pragma unroll
     for (int q = 0; q < MD_GROUP; ++q) s[q] = 0.0;
-    for (int64_t p = int64_t(blockIdx.x) * RED_BLOCK + threadIdx.x; p < n; p += stride) {
-      const double wp = w[p];
+    for (int64_t p = int64_t(blockIdx.x) * RED_BLOCK + threadIdx.x; p < n2; p += stride) {
+      const double2 wp = w2[p];
 #pragma unroll
       for (int q = 0; q < MD_GROUP; ++q) {
         if (q < g) {
           const int i = i0 + q;
-          s[q] = fma(i < nv ? V[int64_t(i) * ld + p] : wp, wp, s[q]);
+          const double2 a = i < nv ? reinterpret_cast<const double2 *>(V + int64_t(i) * ld)[p] : wp;
+          s[q] = fma(a.x, wp.x, fma(a.y, wp.y, s[q]));
         }
       }
     }
@@ -226,15 +248,23 @@ __global__ void reduce_partials_kernel(int nb, int stride, const double *__restr
   }
 }
 
-// w = w - sum_i h_i V_i  (h on the device)
-__global__ __launch_bounds__(256) void multiaxpy_kernel(int64_t n, const double *__restrict__ V, int64_t ld,
+// w = w + sign sum_i h_i V_i  (h on the device), two consecutive entries per lane
+__global__ __launch_bounds__(256) void multiaxpy_kernel(int64_t n2, const double *__restrict__ V, int64_t ld,
                                                         int nv, const double *__restrict__ h,
                                                         double *__restrict__ w, double sign) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += stride) {
-    double acc = 0.0;
-    for (int i = 0; i < nv; ++i) acc += h[i] * V[int64_t(i) * ld + p];
-    w[p] += sign * acc;
+  double2 *w2 = reinterpret_cast<double2 *>(w);
+  for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n2; p += stride) {
+    double ax = 0.0, ay = 0.0;
+    for (int i = 0; i < nv; ++i) {
+      const double2 a = reinterpret_cast<const double2 *>(V + int64_t(i) * ld)[p];
+      ax += h[i] * a.x;
+      ay += h[i] * a.y;
+    }
+    double2 t = w2[p];
+    t.x += sign * ax;
+    t.y += sign * ay;
+    w2[p] = t;
   }
 }
 
@@ -262,15 +292,15 @@ unsigned grid_for(int64_t n, int block) {
 }  // namespace
 
 fo_status spmv(const fo_mesh *mesh, const void *vals, int dtype, const double *x, double *y, hipStream_t s) {
-  const int64_t n = mesh->view.n_dofs / 2;   // nodes
-  const int64_t threads = n * SPMV_LANES;
+  const MeshView &m = mesh->view;
+  const int64_t threads = (m.n_dofs / 2) * SPMV_LANES;
   const unsigned blocks = unsigned((threads + 255) / 256);
   if (dtype == FO_F32)
-    hipLaunchKernelGGL(spmv_kernel<float>, dim3(blocks), dim3(256), 0, s, n, mesh->rowptr, mesh->colidx,
-                       static_cast<const float *>(vals), x, y);
+    hipLaunchKernelGGL(spmv_kernel<float>, dim3(blocks), dim3(256), 0, s, m.V, m.L, m.colptr, mesh->nbr_ptr,
+                       mesh->nbr_idx, static_cast<const float *>(vals), x, y);
   else
-    hipLaunchKernelGGL(spmv_kernel<double>, dim3(blocks), dim3(256), 0, s, n, mesh->rowptr, mesh->colidx,
-                       static_cast<const double *>(vals), x, y);
+    hipLaunchKernelGGL(spmv_kernel<double>, dim3(blocks), dim3(256), 0, s, m.V, m.L, m.colptr, mesh->nbr_ptr,
+                       mesh->nbr_idx, static_cast<const double *>(vals), x, y);
   FO_LAUNCH_CHECK("spmv_kernel");
   return FO_OK;
 }
@@ -297,14 +327,15 @@ fo_status colblock_apply(const fo_mesh *mesh, const double *fac, const double *r
 }
 
 int multidot_blocks(int64_t n) {
-  const int64_t g = (n + 4 * RED_BLOCK - 1) / (4 * RED_BLOCK);
-  return int(g < 2048 ? (g > 0 ? g : 1) : 2048);
+  const int64_t g = (n + 8 * RED_BLOCK - 1) / (8 * RED_BLOCK);
+  return int(g < 1024 ? (g > 0 ? g : 1) : 1024);
 }
 
 fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double *w, double *partial,
                    double *out, hipStream_t s) {
+  if ((n | ld) & 1) return fail(FO_EINVAL, "multidot: vector length and stride must be even");
   const int nb = multidot_blocks(n);
-  hipLaunchKernelGGL(multidot_kernel, dim3(nb), dim3(RED_BLOCK), 0, s, n, V, ld, nv, w, partial);
+  hipLaunchKernelGGL(multidot_kernel, dim3(nb), dim3(RED_BLOCK), 0, s, n / 2, V, ld, nv, w, partial);
   FO_LAUNCH_CHECK("multidot_kernel");
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(nv + 1), dim3(256), 0, s, nb, nv + 1, partial, out);
   FO_LAUNCH_CHECK("reduce_partials_kernel");
@@ -313,7 +344,10 @@ fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double 
 
 fo_status multiaxpy(int64_t n, const double *V, int64_t ld, int nv, const double *h, double *w, double sign,
                     hipStream_t s) {
-  hipLaunchKernelGGL(multiaxpy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, V, ld, nv, h, w, sign);
+  if ((n | ld) & 1) return fail(FO_EINVAL, "multiaxpy: vector length and stride must be even");
+  const int64_t g = (n / 2 + 255) / 256;
+  hipLaunchKernelGGL(multiaxpy_kernel, dim3(unsigned(g < 2048 ? (g > 0 ? g : 1) : 2048)), dim3(256), 0, s, n / 2, V,
+                     ld, nv, h, w, sign);
   FO_LAUNCH_CHECK("multiaxpy_kernel");
   return FO_OK;
 }
