@@ -71,7 +71,8 @@ __global__ __launch_bounds__(256) void spmv_kernel(int V, int L, const int64_t *
 }
 
 // Block-tridiagonal factor of one vertical line (column v): per level k the inverse
-// of the Schur complement S_k (2x2), the coupling to level k-1 (Lo_k) and to k+1 (Up_k).
+// of the Schur complement S_k (2x2), the coupling to level k-1 (Lo_k) and G_k =
+// S_k^{-1} Up_k (Up_k: the coupling to level k+1), which is all the backward sweep needs.
 template <class JT>
 __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const int32_t *__restrict__ self_rank,
                                                               const JT *__restrict__ vals,
@@ -83,8 +84,7 @@ __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const 
   const int sr = self_rank[v];
   const int64_t base = m.colptr[v];
   const int64_t V = m.V;
-  double Sp[4] = {0, 0, 0, 0};      // S_{k-1}^{-1}
-  double Upp[4] = {0, 0, 0, 0};     // Up_{k-1}
+  double Gp[4] = {0, 0, 0, 0};      // G_{k-1} = S_{k-1}^{-1} Up_{k-1}
   for (int k = 0; k <= L; ++k) {
     const int nl = nlev(k, L), kmin = k > 0 ? k - 1 : 0;
     double Dk[4], Lo[4] = {0, 0, 0, 0}, Up[4] = {0, 0, 0, 0};
@@ -98,26 +98,23 @@ __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const 
     }
     if (k > 0) {
       // S_k = D_k - Lo_k S_{k-1}^{-1} Up_{k-1}
-      double T[4];
-      T[0] = Sp[0] * Upp[0] + Sp[1] * Upp[2];
-      T[1] = Sp[0] * Upp[1] + Sp[1] * Upp[3];
-      T[2] = Sp[2] * Upp[0] + Sp[3] * Upp[2];
-      T[3] = Sp[2] * Upp[1] + Sp[3] * Upp[3];
-      Dk[0] -= Lo[0] * T[0] + Lo[1] * T[2];
-      Dk[1] -= Lo[0] * T[1] + Lo[1] * T[3];
-      Dk[2] -= Lo[2] * T[0] + Lo[3] * T[2];
-      Dk[3] -= Lo[2] * T[1] + Lo[3] * T[3];
+      Dk[0] -= Lo[0] * Gp[0] + Lo[1] * Gp[2];
+      Dk[1] -= Lo[0] * Gp[1] + Lo[1] * Gp[3];
+      Dk[2] -= Lo[2] * Gp[0] + Lo[3] * Gp[2];
+      Dk[3] -= Lo[2] * Gp[1] + Lo[3] * Gp[3];
     }
     const double det = Dk[0] * Dk[3] - Dk[1] * Dk[2];
     const double id = 1.0 / det;
     double Si[4] = {Dk[3] * id, -Dk[1] * id, -Dk[2] * id, Dk[0] * id};
+    Gp[0] = Si[0] * Up[0] + Si[1] * Up[2];
+    Gp[1] = Si[0] * Up[1] + Si[1] * Up[3];
+    Gp[2] = Si[2] * Up[0] + Si[3] * Up[2];
+    Gp[3] = Si[2] * Up[1] + Si[3] * Up[3];
     double *Fk = fac + int64_t(k) * 12 * V + v;   // field f of level k at Fk[f V]
     for (int i = 0; i < 4; ++i) {
       Fk[i * V] = Si[i];
       Fk[(4 + i) * V] = Lo[i];
-      Fk[(8 + i) * V] = Up[i];
-      Sp[i] = Si[i];
-      Upp[i] = Up[i];
+      Fk[(8 + i) * V] = Gp[i];
     }
   }
 }
@@ -159,25 +156,26 @@ __global__ __launch_bounds__(128) void colblock_apply_kernel(int V, int L, const
     zv[2 * k] = w0;
     zv[2 * k + 1] = w1;
   }
-  // backward: z_k = w_k - S_k^{-1} Up_k z_{k+1}
+  // backward: z_k = w_k - G_k z_{k+1}, G_k = S_k^{-1} Up_k
   double z0 = zv[2 * L], z1 = zv[2 * L + 1];
-  double g[8], gn[8];
+  double g[4], gn[4];
   {
     const double *Fk = fac + int64_t(L - 1 >= 0 ? L - 1 : 0) * 12 * Vl + v;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { gn[i] = Fk[i * Vl]; gn[4 + i] = Fk[(8 + i) * Vl]; }
+    for (int i = 0; i < 4; ++i) gn[i] = Fk[(8 + i) * Vl];
   }
   for (int k = L - 1; k >= 0; --k) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) g[i] = gn[i];
+    for (int i = 0; i < 4; ++i) g[i] = gn[i];
     if (k > 0) {
       const double *Fn = fac + int64_t(k - 1) * 12 * Vl + v;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) { gn[i] = Fn[i * Vl]; gn[4 + i] = Fn[(8 + i) * Vl]; }
+      for (int i = 0; i < 4; ++i) gn[i] = Fn[(8 + i) * Vl];
     }
-    const double t0 = g[4] * z0 + g[5] * z1, t1 = g[6] * z0 + g[7] * z1;
-    z0 = zv[2 * k] - (g[0] * t0 + g[1] * t1);
-    z1 = zv[2 * k + 1] - (g[2] * t0 + g[3] * t1);
+    const double n0 = zv[2 * k] - (g[0] * z0 + g[1] * z1);
+    const double n1 = zv[2 * k + 1] - (g[2] * z0 + g[3] * z1);
+    z0 = n0;
+    z1 = n1;
     zv[2 * k] = z0;
     zv[2 * k + 1] = z1;
   }
@@ -189,8 +187,9 @@ constexpr int MD_GROUP = 24;   // dot products per pass over a block's chunk
 
 // partial[b * (nv + 1) + i] = sum over block b's rows of V_i . w (i < nv), and w . w (i = nv).
 // Vectors are taken MD_GROUP at a time, so each pass loads w once for all of them and has
-// MD_GROUP independent loads in flight per element pair.  Each lane takes two consecutive
-// entries (16-byte loads; n and ld are even).  Blocks stride through the vectors together
+// 2 MD_GROUP independent loads in flight per iteration: each lane takes two consecutive
+// entries (16-byte loads; n and ld are even) at two places a grid stride apart.  Blocks
+// stride through the vectors together
 // (grid-stride), so at any time the grid reads one window of each vector (DRAM page
 // locality); the summation order is fixed.
 __global__ __launch_bounds__(RED_BLOCK) void multidot_kernel(int64_t n2, const double *__restrict__ V, int64_t ld,
@@ -204,14 +203,19 @@ __global__ __launch_bounds__(RED_BLOCK) void multidot_kernel(int64_t n2, const d
     double s[MD_GROUP];
 #pragma unroll
     for (int q = 0; q < MD_GROUP; ++q) s[q] = 0.0;
-    for (int64_t p = int64_t(blockIdx.x) * RED_BLOCK + threadIdx.x; p < n2; p += stride) {
+    for (int64_t p = int64_t(blockIdx.x) * RED_BLOCK + threadIdx.x; p < n2; p += 2 * stride) {
+      const int64_t p1 = p + stride;
+      const bool two = p1 < n2;
       const double2 wp = w2[p];
+      const double2 wq = two ? w2[p1] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < MD_GROUP; ++q) {
         if (q < g) {
           const int i = i0 + q;
-          const double2 a = i < nv ? reinterpret_cast<const double2 *>(V + int64_t(i) * ld)[p] : wp;
-          s[q] = fma(a.x, wp.x, fma(a.y, wp.y, s[q]));
+          const double2 *Vi = reinterpret_cast<const double2 *>(V + int64_t(i) * ld);
+          const double2 a = i < nv ? Vi[p] : wp;
+          const double2 b = two ? (i < nv ? Vi[p1] : wq) : make_double2(0.0, 0.0);
+          s[q] = fma(a.x, wp.x, fma(a.y, wp.y, fma(b.x, wq.x, fma(b.y, wq.y, s[q]))));
         }
       }
     }
@@ -327,8 +331,8 @@ fo_status colblock_apply(const fo_mesh *mesh, const double *fac, const double *r
 }
 
 int multidot_blocks(int64_t n) {
-  const int64_t g = (n + 8 * RED_BLOCK - 1) / (8 * RED_BLOCK);
-  return int(g < 1024 ? (g > 0 ? g : 1) : 1024);
+  const int64_t g = (n + 16 * RED_BLOCK - 1) / (16 * RED_BLOCK);
+  return int(g < 512 ? (g > 0 ? g : 1) : 512);
 }
 
 fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double *w, double *partial,
