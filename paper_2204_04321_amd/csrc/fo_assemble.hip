@@ -362,6 +362,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
             for (int j = 0; j < NV; ++j) { Jx[a][c][d][j][0] = AT(0); Jx[a][c][d][j][1] = AT(0); }
     }
 
+    AT FA[2][4][2], FH[2][4][2], FB[2][4][3];
     if constexpr (NV == 3) {
       // Wedges.  The residual-only kernel runs the same loop without the tangents, so
       // both kernels produce the same residual bits.  The tangents are accumulated in
@@ -373,7 +374,6 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
       // p = (d zeta/dx, d zeta/dy, d zeta/dz) the same for all j.  So it suffices to sum
       // l0 L and L (x, y parts) over all points, and L . p per triangle point; the six
       // column blocks are formed after the loop.
-      AT FA[2][4][2], FH[2][4][2], FB[2][4][3];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -451,22 +451,6 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
           }
         }
       }
-      // column blocks: with Lam_j = sum_tp lam_j(tp) FB[tp],
-      // lower level: lx_j FA_x + ly_j FA_y - Lam_j; upper: lx_j (FH - FA)_x + ly_j (FH - FA)_y + Lam_j
-#pragma unroll
-      for (int a = 0; a < (JAC ? 2 : 0); ++a)
-#pragma unroll
-        for (int cd = 0; cd < 4; ++cd) {
-          const AT Ux = FH[a][cd][0] - FA[a][cd][0], Uy = FH[a][cd][1] - FA[a][cd][1];
-#pragma unroll
-          for (int j = 0; j < NV; ++j) {
-            const AT lam = fma(AT(Q.lam[0][j]), FB[a][cd][0],
-                               fma(AT(Q.lam[1][j]), FB[a][cd][1], AT(Q.lam[2][j]) * FB[a][cd][2]));
-            const AT hx = AT(lxc[j]), hy = AT(lyc[j]);
-            Jx[a][cd >> 1][cd & 1][j][0] = fma(hx, FA[a][cd][0], fma(hy, FA[a][cd][1], -lam));
-            Jx[a][cd >> 1][cd & 1][j][1] = fma(hx, Ux, fma(hy, Uy, lam));
-          }
-        }
     } else {
 #pragma unroll 1
       for (int q = 0; q < NQ; ++q) {
@@ -617,20 +601,38 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
         const int nlk = nlev(k, L), nl1 = nlev(k + 1, L);
         const int offk = k > 0 ? 1 : 0;     // level k sits at window position 1 unless k = 0
         double *Wk = Jw + cur * max_slot + soff, *Wk1 = Jw + nxt * max_slot + soff;
+        // each (row node, component pair)'s column blocks are added as soon as they are formed
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int j = 0; j < NV; ++j)
+          for (int cd = 0; cd < 4; ++cd) {
+            const int c = cd >> 1, d = cd & 1;
+            if constexpr (NV == 3) {
+              const AT Ux = FH[a][cd][0] - FA[a][cd][0], Uy = FH[a][cd][1] - FA[a][cd][1];
 #pragma unroll
-            for (int lev = 0; lev < 2; ++lev)
-#pragma unroll
-              for (int d = 0; d < 2; ++d) {
-                AT lo = Jx[0][c][d][j][lev];
-                if (CARRY && lev == 0) lo += carry[c][d][j];
-                lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, double(lo));
-                if (CARRY && lev == 1 && k + 1 < L) carry[c][d][j] = Jx[1][c][d][j][1];
-                else lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, double(Jx[1][c][d][j][lev]));
+              for (int j = 0; j < NV; ++j) {
+                const AT lam = fma(AT(Q.lam[0][j]), FB[a][cd][0],
+                                   fma(AT(Q.lam[1][j]), FB[a][cd][1], AT(Q.lam[2][j]) * FB[a][cd][2]));
+                const AT hx = AT(lxc[j]), hy = AT(lyc[j]);
+                Jx[a][c][d][j][0] = fma(hx, FA[a][cd][0], fma(hy, FA[a][cd][1], -lam));
+                Jx[a][c][d][j][1] = fma(hx, Ux, fma(hy, Uy, lam));
               }
+            }
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+#pragma unroll
+              for (int lev = 0; lev < 2; ++lev) {
+                if (a == 0) {
+                  AT lo = Jx[0][c][d][j][lev];
+                  if (CARRY && lev == 0) lo += carry[c][d][j];
+                  lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, double(lo));
+                } else if (CARRY && lev == 1 && k + 1 < L) {
+                  carry[c][d][j] = Jx[1][c][d][j][1];
+                } else {
+                  lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, double(Jx[1][c][d][j][lev]));
+                }
+              }
+          }
       }
     }
     wave_sync();
