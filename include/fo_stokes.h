@@ -103,7 +103,9 @@ fo_status fo_assemble_residual(const fo_mesh *mesh, const double *U_dev, double 
  * FO_F32: float; with FO_F32 the per-cell derivatives are computed in FP32 over
  * an FP64 primal evaluation, summed over cells in FP64 and rounded once).  kind = FO_JAC_PICARD drops the viscosity-derivative
  * term.  If R_dev is not NULL the FP64 residual is written too, from the same
- * pass.  Jvals and R are overwritten. */
+ * pass.  Jvals and R are overwritten.  FO_EINVAL, before any device work, for a
+ * wedge mesh whose Glen exponent is not 3 (hexahedral meshes take any n >= 1; the
+ * residual of either element takes any n). */
 fo_status fo_assemble_jacobian(const fo_mesh *mesh, const double *U_dev, double *R_dev,
                                void *Jvals_dev, int32_t dtype, int32_t kind, void *stream);
 
@@ -156,7 +158,9 @@ size_t fo_newton_workspace_bytes(const fo_mesh *mesh, const fo_newton_opts *opts
  * [n_dofs] holds the initial guess (unless init = FO_INIT_SIA) and returns the last
  * accepted iterate.  workspace_dev: caller-owned device memory, 256-byte aligned, at
  * least fo_newton_workspace_bytes.  Returns FO_OK on convergence, FO_ENOTCONV (cap or
- * line search), FO_ENONFINITE; the report is filled in every case.  Synchronises. */
+ * line search), FO_ENONFINITE; the report is filled in every case.  Synchronises.
+ * FO_EINVAL (nothing run, report untouched) for a wedge mesh with Glen exponent != 3,
+ * whose Jacobian is not available. */
 fo_status fo_newton_solve(const fo_mesh *mesh, double *U_dev, const fo_newton_opts *opts,
                           fo_newton_report *report, void *workspace_dev, size_t workspace_bytes,
                           void *stream);
@@ -174,7 +178,10 @@ void fo_ensemble_destroy(fo_ensemble *ens);
  * items from a device counter until all are done.  U_dev, R_dev, J_dev are host arrays of
  * n_members device pointers laid out as for fo_assemble_jacobian (R_dev may be NULL, or hold
  * NULL entries, to skip residuals).  J_dev == NULL assembles residuals only (R_dev required).
- * Each member's result equals its own fo_assemble_jacobian / fo_assemble_residual. */
+ * Each member's result equals its own fo_assemble_jacobian / fo_assemble_residual bit
+ * for bit when every member has n = 3 or none has; in a mixed ensemble all members take
+ * the general power law, which agrees with the n = 3 evaluation to rounding.  Wedge
+ * members with n != 3 make a Jacobian request fail with FO_EINVAL. */
 fo_status fo_ensemble_assemble(fo_ensemble *ens, const double *const *U_dev, double *const *R_dev,
                                void *const *J_dev, int32_t dtype, int32_t kind, void *stream);
 

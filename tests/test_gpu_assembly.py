@@ -48,6 +48,28 @@ def _graded_sigma(m):
     return m.with_fields(sigma=sg)
 
 
+def _fan(n_cells=64, L=3, seed=8):
+    """One vertex in n_cells triangles (64 is the per-vertex maximum), ring vertices with 2 or 3 cells."""
+    rng = np.random.default_rng(seed)
+    ang = np.sort(rng.uniform(0, 2 * np.pi, n_cells))
+    r = 3e3 * (1 + 0.2 * rng.uniform(-1, 1, n_cells))
+    xy = np.vstack([[0.0, 0.0], np.stack([r * np.cos(ang), r * np.sin(ang)], 1)])
+    cells = np.array([[0, 1 + i, 1 + (i + 1) % n_cells] for i in range(n_cells)], dtype=np.int32)
+    V = xy.shape[0]
+    H = 600 + 100 * rng.uniform(size=V)
+    m = ExtrudedMesh("wedge", xy, cells, 200 - 0.01 * xy[:, 0] + H, H, 400 + 300 * rng.uniform(size=V),
+                     np.linspace(0, 1, L + 1))
+    return m, smooth_velocity(m, rng, 60.0, 0.05)
+
+
+def _free_slip_patch(seed=9):
+    """beta = 0 on part of the bed (free slip there)."""
+    m, U = _box(5, 4, 3, "wedge", seed)
+    beta = m.beta.copy()
+    beta[m.xy[:, 0] < 2e3] = 0.0
+    return m.with_fields(beta=beta), U
+
+
 CASES = {
     "slab_hex_2000": lambda: config0_slab(),
     "ellipse_wedge_ragged": lambda: _small_ellipse(),
@@ -60,7 +82,24 @@ CASES = {
                         np.random.default_rng(6).normal(size=16) * 30),
     "one_wedge": lambda: (right_wedge_single(600., 900., 250., 300.),
                           np.random.default_rng(7).normal(size=12) * 30),
+    # Glen exponents other than 3 take the general power-law viscosity path
+    "glen_n1_wedge": lambda: (lambda mu: (mu[0].with_fields(n=1.0, A=2e-13), mu[1]))(_box(4, 3, 3, "wedge", 10)),
+    "glen_n2p5_hex": lambda: (lambda mu: (mu[0].with_fields(n=2.5, A=3e-15), mu[1]))(_box(3, 3, 2, "hex", 11)),
+    "fan_64_cells_at_a_vertex": lambda: _fan(),
+    "free_slip_patch": lambda: _free_slip_patch(),
 }
+
+
+def _wedge_general_n(m):
+    """Wedge Jacobians exist for n = 3 only (the residual and hexahedral meshes take any n)."""
+    return m.elem == "wedge" and m.n != 3.0
+
+
+def _assert_jacobian_rejected(M, U):
+    from paper_2204_04321_amd._lib import FoError
+    for dtype in ("f64", "f32"):
+        with pytest.raises(FoError, match="n != 3"):
+            gpu_jacobian(M, U, dtype)
 
 
 @pytest.fixture(scope="module", params=sorted(CASES))
@@ -83,6 +122,9 @@ def test_pattern_matches_oracle(case):
 @pytest.mark.parametrize("kind", ["newton", "picard"])
 def test_jacobian_f64_parity(case, kind):
     name, m, U, M = case
+    if _wedge_general_n(m):
+        _assert_jacobian_rejected(M, U)
+        return
     R, J = gpu_jacobian(M, U, "f64", kind)
     Ro, Jo = fo.assemble(m, U, picard=(kind == "picard"))
     rs, js = fo.abs_scales(m, U, picard=(kind == "picard"))
@@ -103,6 +145,9 @@ def test_residual_f64_parity(case):
 
 def test_jacobian_f32_bound(case):
     name, m, U, M = case
+    if _wedge_general_n(m):
+        _assert_jacobian_rejected(M, U)
+        return
     R, J = gpu_jacobian(M, U, "f32", "newton")
     Ro, Jo = fo.assemble(m, U)
     rs, js = fo.abs_scales(m, U)
@@ -124,6 +169,10 @@ def test_sia_parity(case):
 def test_repeatability(case):
     """Owner-computes assembly has no global atomics: two runs are bitwise identical."""
     name, m, U, M = case
+    if _wedge_general_n(m):
+        assert np.array_equal(gpu_residual(M, U), gpu_residual(M, U))
+        _assert_jacobian_rejected(M, U)
+        return
     R1, J1 = gpu_jacobian(M, U)
     R2, J2 = gpu_jacobian(M, U)
     assert np.array_equal(J1.data, J2.data)
@@ -135,6 +184,13 @@ def test_outputs_fully_overwritten(case):
     """No zero fill is needed: stale values in the output buffers never leak through."""
     name, m, U, M = case
     Ud = to_dev(U)
+    if _wedge_general_n(m):
+        R0 = M.residual(Ud)
+        Rn = torch.full_like(R0, float("nan"))
+        M.residual(Ud, out=Rn)
+        torch.cuda.synchronize()
+        assert torch.equal(Rn, R0)
+        return
     R0, J0 = M.jacobian(Ud)
     Rn = torch.full_like(R0, float("nan"))
     Jn = torch.full_like(J0, float("nan"))

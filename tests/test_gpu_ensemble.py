@@ -95,3 +95,29 @@ def test_hexahedral_ensemble_equals_single_mesh():
     rs, js = fo.abs_scales(m, U)
     er, ej = row_scaled_errors(R1, J1, Ro, Jo, rs, js)
     assert er <= 1e-12 and ej <= 1e-12
+
+
+def test_wedge_ensemble_with_general_exponent():
+    """A wedge member with n != 3: the residual-only launch is correct for every member, a
+    Jacobian request is rejected before any launch (wedge Jacobians exist for n = 3 only)."""
+    from test_gpu_assembly import _box
+    from paper_2204_04321_amd._lib import FoError
+    from paper_2204_04321_amd.api import Ensemble
+    mus = [_box(4, 3, 2, "wedge", 50), _box(5, 4, 3, "wedge", 51)]
+    mus[1] = (mus[1][0].with_fields(n=1.0, A=2e-13), mus[1][1])
+    Ms = [gpu_mesh(m) for m, _ in mus]
+    E = Ensemble(Ms)
+    Us = [to_dev(U) for _, U in mus]
+    Rs = [torch.full((M.n_dofs,), float("nan"), dtype=torch.float64, device="cuda") for M in Ms]
+    E.assemble(Us, Rs)
+    torch.cuda.synchronize()
+    # a mixed ensemble takes the general power law for every member: the n != 3 member equals
+    # its own residual bit for bit, the n = 3 one agrees with the oracle to 1e-12
+    assert torch.equal(Rs[1], Ms[1].residual(Us[1]))
+    for (m, U), R in zip(mus, Rs):
+        Ro = fo.residual(m, U)
+        rs, _ = fo.abs_scales(m, U)
+        assert np.max(np.abs(R.cpu().numpy() - Ro) / rs) <= 1e-12
+    Js = [torch.empty(M.nnz, dtype=torch.float64, device="cuda") for M in Ms]
+    with pytest.raises(FoError, match="n != 3"):
+        E.assemble(Us, Rs, Js)

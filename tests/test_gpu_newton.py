@@ -83,3 +83,14 @@ def test_newton_rejects_bad_options(cap):
     U = to_dev(solve.sia_guess(m))
     with pytest.raises(ValueError):
         M.newton_solve(U, gmres_restart=0)
+
+
+def test_newton_rejects_wedge_general_exponent(cap):
+    """Wedge meshes with n != 3 have no Jacobian: the solve returns FO_EINVAL before any work."""
+    m, _, _ = cap
+    M1 = gpu_mesh(m.with_fields(n=1.0, A=2e-13))
+    U = to_dev(solve.sia_guess(m))
+    U0 = U.clone()
+    rep = M1.newton_solve(U, tol=1e-8)
+    assert rep["status"] == -1 and "n = 3" in rep["message"]
+    assert torch.equal(U, U0)
