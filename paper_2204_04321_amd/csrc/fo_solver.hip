@@ -19,6 +19,7 @@ __device__ __forceinline__ int nlev(int k, int L) { return (k == 0 || k == L) ? 
 __device__ __forceinline__ int cumlev(int k) { return k == 0 ? 0 : 3 * k - 1; }
 
 constexpr int SPMV_LANES = 8;   // lanes per node (pair of rows)
+constexpr int APPLY_MAX_THREADS = 64;   // columns per preconditioner-apply block
 
 template <class JT> struct Pair2;
 template <> struct Pair2<double> { using T = double2; };
@@ -121,64 +122,72 @@ __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const 
 
 // z = M^{-1} r for every vertical line (forward then backward block substitution).  The
 // factors are stored level-major with the vertex index fastest, so a wave's loads of one
-// factor field are contiguous.
-__global__ __launch_bounds__(128) void colblock_apply_kernel(int V, int L, const double *__restrict__ fac,
-                                                             const double *__restrict__ r,
-                                                             double *__restrict__ z) {
-  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  const int64_t Vl = V;
-  const double *rv = r + int64_t(v) * 2 * (L + 1);
-  double *zv = z + int64_t(v) * 2 * (L + 1);
-  // forward: y_k = r_k - Lo_k S_{k-1}^{-1} y_{k-1}; keep w_k = S_k^{-1} y_k in z.  The
-  // next level's factors and right-hand side are loaded one level ahead.
-  double f[8], fn[8], rn0 = rv[0], rn1 = rv[1];
+// factor field are contiguous.  A block's columns are contiguous in r and z (2 (L+1) values
+// each): they are copied through LDS with coalesced loads and stores, and each thread runs
+// its column's two sweeps in place in LDS.
+__global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V, int L, const double *__restrict__ fac,
+                                                                           const double *__restrict__ r,
+                                                                           double *__restrict__ z) {
+  extern __shared__ double col_sh[];   // [blockDim.x][2 (L + 1)]
+  const int n = 2 * (L + 1);
+  const int64_t v0 = int64_t(blockIdx.x) * blockDim.x;
+  const int nv = int(V - v0 < int64_t(blockDim.x) ? V - v0 : int64_t(blockDim.x));
+  for (int e = threadIdx.x; e < nv * n; e += blockDim.x) col_sh[e] = r[v0 * n + e];
+  __syncthreads();
+  if (int(threadIdx.x) < nv) {
+    const int64_t v = v0 + threadIdx.x;
+    const int64_t Vl = V;
+    double *zv = col_sh + threadIdx.x * n;   // holds r, then w, then z
+    // forward: y_k = r_k - Lo_k S_{k-1}^{-1} y_{k-1}; keep w_k = S_k^{-1} y_k.  The next
+    // level's factors are loaded one level ahead.
+    double f[8], fn[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) fn[i] = fac[int64_t(i) * Vl + v];
-  double w0 = 0, w1 = 0;
-  for (int k = 0; k <= L; ++k) {
+    for (int i = 0; i < 8; ++i) fn[i] = fac[int64_t(i) * Vl + v];
+    double w0 = 0, w1 = 0;
+    for (int k = 0; k <= L; ++k) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) f[i] = fn[i];
-    double y0 = rn0, y1 = rn1;
-    if (k < L) {
-      const double *Fn = fac + int64_t(k + 1) * 12 * Vl + v;
+      for (int i = 0; i < 8; ++i) f[i] = fn[i];
+      double y0 = zv[2 * k], y1 = zv[2 * k + 1];
+      if (k < L) {
+        const double *Fn = fac + int64_t(k + 1) * 12 * Vl + v;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) fn[i] = Fn[i * Vl];
-      rn0 = rv[2 * k + 2];
-      rn1 = rv[2 * k + 3];
+        for (int i = 0; i < 8; ++i) fn[i] = Fn[i * Vl];
+      }
+      if (k > 0) {
+        y0 -= f[4] * w0 + f[5] * w1;
+        y1 -= f[6] * w0 + f[7] * w1;
+      }
+      w0 = f[0] * y0 + f[1] * y1;
+      w1 = f[2] * y0 + f[3] * y1;
+      zv[2 * k] = w0;
+      zv[2 * k + 1] = w1;
     }
-    if (k > 0) {
-      y0 -= f[4] * w0 + f[5] * w1;
-      y1 -= f[6] * w0 + f[7] * w1;
+    // backward: z_k = w_k - G_k z_{k+1}, G_k = S_k^{-1} Up_k
+    double z0 = zv[2 * L], z1 = zv[2 * L + 1];
+    double g[4], gn[4];
+    {
+      const double *Fk = fac + int64_t(L - 1 >= 0 ? L - 1 : 0) * 12 * Vl + v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) gn[i] = Fk[(8 + i) * Vl];
     }
-    w0 = f[0] * y0 + f[1] * y1;
-    w1 = f[2] * y0 + f[3] * y1;
-    zv[2 * k] = w0;
-    zv[2 * k + 1] = w1;
-  }
-  // backward: z_k = w_k - G_k z_{k+1}, G_k = S_k^{-1} Up_k
-  double z0 = zv[2 * L], z1 = zv[2 * L + 1];
-  double g[4], gn[4];
-  {
-    const double *Fk = fac + int64_t(L - 1 >= 0 ? L - 1 : 0) * 12 * Vl + v;
+    for (int k = L - 1; k >= 0; --k) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) gn[i] = Fk[(8 + i) * Vl];
-  }
-  for (int k = L - 1; k >= 0; --k) {
+      for (int i = 0; i < 4; ++i) g[i] = gn[i];
+      if (k > 0) {
+        const double *Fn = fac + int64_t(k - 1) * 12 * Vl + v;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) g[i] = gn[i];
-    if (k > 0) {
-      const double *Fn = fac + int64_t(k - 1) * 12 * Vl + v;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) gn[i] = Fn[(8 + i) * Vl];
+        for (int i = 0; i < 4; ++i) gn[i] = Fn[(8 + i) * Vl];
+      }
+      const double n0 = zv[2 * k] - (g[0] * z0 + g[1] * z1);
+      const double n1 = zv[2 * k + 1] - (g[2] * z0 + g[3] * z1);
+      z0 = n0;
+      z1 = n1;
+      zv[2 * k] = z0;
+      zv[2 * k + 1] = z1;
     }
-    const double n0 = zv[2 * k] - (g[0] * z0 + g[1] * z1);
-    const double n1 = zv[2 * k + 1] - (g[2] * z0 + g[3] * z1);
-    z0 = n0;
-    z1 = n1;
-    zv[2 * k] = z0;
-    zv[2 * k + 1] = z1;
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nv * n; e += blockDim.x) z[v0 * n + e] = col_sh[e];
 }
 
 constexpr int RED_BLOCK = 256;
@@ -324,8 +333,12 @@ fo_status colblock_factor(const fo_mesh *mesh, const void *vals, int dtype, doub
 
 fo_status colblock_apply(const fo_mesh *mesh, const double *fac, const double *r, double *z, hipStream_t s) {
   const MeshView &m = mesh->view;
-  const unsigned blocks = unsigned((m.V + 127) / 128);
-  hipLaunchKernelGGL(colblock_apply_kernel, dim3(blocks), dim3(128), 0, s, m.V, m.L, fac, r, z);
+  // columns per block: the block's columns (2 (L+1) doubles each) stay within 64 KB of LDS
+  const size_t col_bytes = size_t(2) * (m.L + 1) * sizeof(double);
+  int tpb = APPLY_MAX_THREADS;
+  while (tpb > 1 && tpb * col_bytes > 65536) tpb /= 2;
+  const unsigned blocks = unsigned((m.V + tpb - 1) / tpb);
+  hipLaunchKernelGGL(colblock_apply_kernel, dim3(blocks), dim3(tpb), tpb * col_bytes, s, m.V, m.L, fac, r, z);
   FO_LAUNCH_CHECK("colblock_apply_kernel");
   return FO_OK;
 }
