@@ -86,6 +86,7 @@ CASES = {
     "glen_n1_wedge": lambda: (lambda mu: (mu[0].with_fields(n=1.0, A=2e-13), mu[1]))(_box(4, 3, 3, "wedge", 10)),
     "glen_n2p5_hex": lambda: (lambda mu: (mu[0].with_fields(n=2.5, A=3e-15), mu[1]))(_box(3, 3, 2, "hex", 11)),
     "fan_64_cells_at_a_vertex": lambda: _fan(),
+    "ellipse_wedge_20_layers": lambda: _small_ellipse(seed=12, n_points=200, L=20),
     "free_slip_patch": lambda: _free_slip_patch(),
 }
 
