@@ -103,9 +103,9 @@ fo_status fo_assemble_residual(const fo_mesh *mesh, const double *U_dev, double 
  * FO_F32: float; with FO_F32 the per-cell derivatives are computed in FP32 over
  * an FP64 primal evaluation, summed over cells in FP64 and rounded once).  kind = FO_JAC_PICARD drops the viscosity-derivative
  * term.  If R_dev is not NULL the FP64 residual is written too, from the same
- * pass.  Jvals and R are overwritten.  FO_EINVAL, before any device work, for a
- * wedge mesh whose Glen exponent is not 3 (hexahedral meshes take any n >= 1; the
- * residual of either element takes any n). */
+ * pass.  Jvals and R are overwritten.  Any Glen exponent n >= 1, for either element;
+ * n = 3 takes a dedicated viscosity evaluation that agrees with the general power
+ * law to rounding. */
 fo_status fo_assemble_jacobian(const fo_mesh *mesh, const double *U_dev, double *R_dev,
                                void *Jvals_dev, int32_t dtype, int32_t kind, void *stream);
 
@@ -158,9 +158,7 @@ size_t fo_newton_workspace_bytes(const fo_mesh *mesh, const fo_newton_opts *opts
  * [n_dofs] holds the initial guess (unless init = FO_INIT_SIA) and returns the last
  * accepted iterate.  workspace_dev: caller-owned device memory, 256-byte aligned, at
  * least fo_newton_workspace_bytes.  Returns FO_OK on convergence, FO_ENOTCONV (cap or
- * line search), FO_ENONFINITE; the report is filled in every case.  Synchronises.
- * FO_EINVAL (nothing run, report untouched) for a wedge mesh with Glen exponent != 3,
- * whose Jacobian is not available. */
+ * line search), FO_ENONFINITE; the report is filled in every case.  Synchronises. */
 fo_status fo_newton_solve(const fo_mesh *mesh, double *U_dev, const fo_newton_opts *opts,
                           fo_newton_report *report, void *workspace_dev, size_t workspace_bytes,
                           void *stream);
@@ -180,8 +178,7 @@ void fo_ensemble_destroy(fo_ensemble *ens);
  * NULL entries, to skip residuals).  J_dev == NULL assembles residuals only (R_dev required).
  * Each member's result equals its own fo_assemble_jacobian / fo_assemble_residual bit
  * for bit when every member has n = 3 or none has; in a mixed ensemble all members take
- * the general power law, which agrees with the n = 3 evaluation to rounding.  Wedge
- * members with n != 3 make a Jacobian request fail with FO_EINVAL. */
+ * the general power law, which agrees with the n = 3 evaluation to rounding. */
 fo_status fo_ensemble_assemble(fo_ensemble *ens, const double *const *U_dev, double *const *R_dev,
                                void *const *J_dev, int32_t dtype, int32_t kind, void *stream);
 

@@ -35,6 +35,11 @@
 
 #include "fo_internal.h"
 
+// Multiply-adds are fused only where one source expression holds both operations, so
+// the residual-only, R+J and ensemble kernels, which share the element arithmetic, round
+// it identically (fusion chosen by the backend depends on each kernel's other uses).
+#pragma clang fp contract(on)
+
 namespace fo {
 namespace {
 
@@ -146,9 +151,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-template <class T>
-__device__ __forceinline__ T sel4(int i, T a, T b, T c, T d) {
-  return i == 0 ? a : (i == 1 ? b : (i == 2 ? c : d));
+// Picks a, b, c or d by a lane-varying index i (d for any i outside 0..2) without a branch:
+// all four operands are evaluated and combined through bit masks.  Written as a compare
+// chain, the selection becomes a switch, i.e. a divergent branch tree, and the register
+// allocator has placed copies of values that stay live across it inside the masked part,
+// so lanes outside the mask later read copies they never wrote.
+__device__ __forceinline__ double sel4(int i, double a, double b, double c, double d) {
+  using u64 = unsigned long long;
+  const u64 m0 = 0ull - u64(i == 0), m1 = 0ull - u64(i == 1), m2 = 0ull - u64(i == 2);
+  const u64 m3 = ~(m0 | m1 | m2);
+  const u64 r = (__builtin_bit_cast(u64, a) & m0) | (__builtin_bit_cast(u64, b) & m1) |
+                (__builtin_bit_cast(u64, c) & m2) | (__builtin_bit_cast(u64, d) & m3);
+  return __builtin_bit_cast(double, r);
 }
 
 // One wave = one task (a run of vertex columns); one lane = one (v, t) item.
@@ -765,19 +779,10 @@ fo_status launch_t(const fo_mesh *mesh, const double *U, double *R, JT *J, int k
   return profile_end(mesh, s);
 }
 
-// Wedge Jacobians are built for n = 3 only: the general power-law wedge R+J kernel, compiled
-// at two waves per SIMD, returned wrong and run-to-run varying values, and at one wave per
-// SIMD it faulted; the cause is not identified, so that instantiation is not compiled and the
-// request is rejected (the general-exponent wedge residual and all hexahedral kernels pass).
-constexpr const char *kWedgeJacN3 =
-    "Jacobian of a wedge mesh with Glen exponent n != 3 is not supported (residual and hexahedral "
-    "meshes are)";
-
 template <int NV, bool JAC, class JT>
 fo_status launch_n(const fo_mesh *mesh, const double *U, double *R, JT *J, int kind, hipStream_t s) {
   if (mesh->view.n_glen == 3.0) return launch_t<NV, JAC, JT, true>(mesh, U, R, J, kind, s);
-  if constexpr (NV == 3 && JAC) return fail(FO_EINVAL, std::string("fo_assemble_jacobian: ") + kWedgeJacN3);
-  else return launch_t<NV, JAC, JT, false>(mesh, U, R, J, kind, s);
+  return launch_t<NV, JAC, JT, false>(mesh, U, R, J, kind, s);
 }
 
 template <int NV, bool JAC, class JT, bool N3>
@@ -801,8 +806,7 @@ fo_status launch_ens_t(const EnsembleLaunch &E, int kind, hipStream_t s) {
 template <int NV, bool JAC, class JT>
 fo_status launch_ens_n(const EnsembleLaunch &E, int kind, hipStream_t s) {
   if (E.all_n3) return launch_ens_t<NV, JAC, JT, true>(E, kind, s);
-  if constexpr (NV == 3 && JAC) return fail(FO_EINVAL, std::string("fo_ensemble_assemble: ") + kWedgeJacN3);
-  else return launch_ens_t<NV, JAC, JT, false>(E, kind, s);
+  return launch_ens_t<NV, JAC, JT, false>(E, kind, s);
 }
 
 }  // namespace

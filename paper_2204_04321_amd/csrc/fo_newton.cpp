@@ -201,8 +201,6 @@ extern "C" size_t fo_newton_workspace_bytes(const fo_mesh *m, const fo_newton_op
 extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newton_opts *o,
                                      fo_newton_report *rep, void *ws, size_t ws_bytes, void *stream) {
   if (!m || !U || !o || !rep || !ws) return fail(FO_EINVAL, "fo_newton_solve: NULL argument");
-  if (m->view.nv == 3 && m->view.n_glen != 3.0)
-    return fail(FO_EINVAL, "fo_newton_solve: wedge meshes need Glen exponent n = 3 (no general-n wedge Jacobian)");
   if (o->gmres_restart < 1 || o->gmres_restart > 500 || o->max_lin < 1 || o->max_newton < 0 ||
       !(o->tol > 0) || !(o->lin_rtol > 0) || o->max_backtracks < 0 ||
       (o->jac_dtype != FO_F64 && o->jac_dtype != FO_F32) || (o->init != FO_INIT_USER && o->init != FO_INIT_SIA))

@@ -98,10 +98,9 @@ def test_hexahedral_ensemble_equals_single_mesh():
 
 
 def test_wedge_ensemble_with_general_exponent():
-    """A wedge member with n != 3: the residual-only launch is correct for every member, a
-    Jacobian request is rejected before any launch (wedge Jacobians exist for n = 3 only)."""
+    """A wedge member with n != 3 beside an n = 3 one: residual and both Jacobian types agree
+    with the oracle for every member (a mixed ensemble takes the general power law for all)."""
     from test_gpu_assembly import _box
-    from paper_2204_04321_amd._lib import FoError
     from paper_2204_04321_amd.api import Ensemble
     mus = [_box(4, 3, 2, "wedge", 50), _box(5, 4, 3, "wedge", 51)]
     mus[1] = (mus[1][0].with_fields(n=1.0, A=2e-13), mus[1][1])
@@ -111,13 +110,26 @@ def test_wedge_ensemble_with_general_exponent():
     Rs = [torch.full((M.n_dofs,), float("nan"), dtype=torch.float64, device="cuda") for M in Ms]
     E.assemble(Us, Rs)
     torch.cuda.synchronize()
-    # a mixed ensemble takes the general power law for every member: the n != 3 member equals
-    # its own residual bit for bit, the n = 3 one agrees with the oracle to 1e-12
+    # the n != 3 member equals its own residual bit for bit, the n = 3 one agrees with the
+    # oracle to 1e-12 (general power law instead of the n = 3 evaluation)
     assert torch.equal(Rs[1], Ms[1].residual(Us[1]))
     for (m, U), R in zip(mus, Rs):
         Ro = fo.residual(m, U)
         rs, _ = fo.abs_scales(m, U)
         assert np.max(np.abs(R.cpu().numpy() - Ro) / rs) <= 1e-12
-    Js = [torch.empty(M.nnz, dtype=torch.float64, device="cuda") for M in Ms]
-    with pytest.raises(FoError, match="n != 3"):
-        E.assemble(Us, Rs, Js)
+    import scipy.sparse as sp
+    for dtype, tdt, tol in (("f64", torch.float64, 1e-12), ("f32", torch.float32, 1e-5)):
+        Js = [torch.full((M.nnz,), float("nan"), dtype=tdt, device="cuda") for M in Ms]
+        E.assemble(Us, Rs, Js, dtype=dtype)
+        torch.cuda.synchronize()
+        R1, J1 = Ms[1].jacobian(Us[1], dtype=dtype)
+        torch.cuda.synchronize()
+        assert torch.equal(Rs[1], R1) and torch.equal(Js[1], J1)
+        for (m, U), R, J, M in zip(mus, Rs, Js, Ms):
+            rowptr, colidx = M.pattern()
+            Jg = sp.csr_matrix((J.double().cpu().numpy(), colidx.cpu().numpy().astype(np.int64),
+                                rowptr.cpu().numpy()), shape=(M.n_dofs, M.n_dofs))
+            Ro, Jo = fo.assemble(m, U)
+            rs, js = fo.abs_scales(m, U)
+            er, ej = row_scaled_errors(R.cpu().numpy(), Jg, Ro, Jo, rs, js)
+            assert er <= 1e-12 and ej <= tol, (dtype, er, ej)
