@@ -165,6 +165,16 @@ __device__ __forceinline__ double sel4(int i, double a, double b, double c, doub
   return __builtin_bit_cast(double, r);
 }
 
+// Two consecutive Jacobian entries as one streaming (nontemporal) store; p is 8-entry aligned.
+template <class JT>
+__device__ __forceinline__ void store2_nt(JT *p, double x, double y) {
+  typedef JT v2 __attribute__((ext_vector_type(2)));
+  v2 t;
+  t.x = JT(x);
+  t.y = JT(y);
+  __builtin_nontemporal_store(t, reinterpret_cast<v2 *>(p));
+}
+
 // One wave = one task (a run of vertex columns); one lane = one (v, t) item.
 // N3 selects the n = 3 viscosity power; JAC adds the Jacobian; JT is its value type
 // (double, or float with FP32 derivative arithmetic over the FP64 primal).
@@ -683,14 +693,12 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
             double *src = wb + so[i];
             const int e = 2 * lane;   // nn is a multiple of 4, so e < nn implies e + 1 < nn
             if (e < nn[i]) {
-              dst[e] = JT(val[i].x);
-              dst[e + 1] = JT(val[i].y);
+              store2_nt(dst + e, val[i].x, val[i].y);
               *reinterpret_cast<double2 *>(src + e) = make_double2(0.0, 0.0);
             }
             for (int f = e + 2 * WAVE; f < nn[i]; f += 2 * WAVE) {
               const double2 w = *reinterpret_cast<const double2 *>(src + f);
-              dst[f] = JT(w.x);
-              dst[f + 1] = JT(w.y);
+              store2_nt(dst + f, w.x, w.y);
               *reinterpret_cast<double2 *>(src + f) = make_double2(0.0, 0.0);
             }
           }
