@@ -139,6 +139,12 @@ __device__ __forceinline__ double rcbrt64(double x) {
   return fma(y * r, fma(2.0 / 9.0, r, 1.0 / 3.0), y);
 }
 
+// q^p for the viscosity power, q = eps_e^2 + eps0^2 >= 0: exp2(p log2 q), which needs none
+// of the general pow's cases for negative or special arguments; p = 0 (n = 1) gives 1.
+__device__ __forceinline__ double powq(double q, double p) {
+  return p == 0.0 ? 1.0 : exp2(p * log2(q));
+}
+
 template <class T>
 __device__ __forceinline__ void lds_add(T *p, T v) {
   atomicAdd(p, v);   // LDS atomics: lanes of one wave may hit the same entry
@@ -436,7 +442,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
           const double qe = qq + m.eps0_sq;
           double mu;
           if constexpr (N3) mu = m.visc_pref * rcbrt64(qe);
-          else mu = m.visc_pref * pow(qe, m.visc_exp);
+          else mu = m.visc_pref * powq(qe, m.visc_exp);
           const double s2 = 2.0 * mu * W;
           const double t2 = picard ? 0.0 : 2.0 * (m.visc_exp * mu * rcp64(qe)) * W;
           const double e1x = 2.0 * exx + eyy, e1y = exy, e1z = exz;
@@ -541,7 +547,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
         const double qe = qq + m.eps0_sq;
         double mu;
         if constexpr (N3) mu = m.visc_pref * rcbrt64(qe);
-        else mu = m.visc_pref * pow(qe, m.visc_exp);
+        else mu = m.visc_pref * powq(qe, m.visc_exp);
         const double s2 = 2.0 * mu * W;
         const double t2 = picard ? 0.0 : 2.0 * (m.visc_exp * mu * rcp64(qe)) * W;
         const double e1x = 2.0 * exx + eyy, e1y = exy, e1z = exz;
