@@ -41,7 +41,7 @@ Layout layout(const fo_mesh *m, const fo_newton_opts *o) {
   L.W = take(8 * n);
   L.Z = take(8 * n);
   L.T = take(8 * n);
-  L.fac = take(8 * size_t(m->view.V) * size_t(m->view.L + 1) * 12);
+  L.fac = take(4 * size_t(m->view.V) * size_t(m->view.L + 1) * 12);
   L.V = take(8 * n * size_t(mres + 1));
   L.partial = take(8 * size_t(multidot_blocks(int64_t(n))) * size_t(mres + 2));
   L.dots = take(8 * size_t(mres + 2));
@@ -82,7 +82,7 @@ fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b
   double *w = c.dptr(c.L.W);
   double *z = c.dptr(c.L.Z);
   double *t = c.dptr(c.L.T);
-  double *fac = c.dptr(c.L.fac);
+  float *fac = reinterpret_cast<float *>(c.ws + c.L.fac);
   fo_status st;
   its = 0;
   double bnorm;
@@ -256,7 +256,7 @@ extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newto
     rep->jacobian_calls++;
     // Preconditioner Construction
     t0 = std::chrono::steady_clock::now();
-    if ((st = colblock_factor(m, Jv, o->jac_dtype, c.dptr(c.L.fac), c.s)) != FO_OK) return st;
+    if ((st = colblock_factor(m, Jv, o->jac_dtype, reinterpret_cast<float *>(c.ws + c.L.fac), c.s)) != FO_OK) return st;
     FO_HIP_TRY(hipStreamSynchronize(c.s));
     rep->ms_prec_construction += ms_since(t0);
     // Linear Solve: J dU = -R

@@ -74,10 +74,12 @@ __global__ __launch_bounds__(256) void spmv_kernel(int V, int L, const int64_t *
 // Block-tridiagonal factor of one vertical line (column v): per level k the inverse
 // of the Schur complement S_k (2x2), the coupling to level k-1 (Lo_k) and G_k =
 // S_k^{-1} Up_k (Up_k: the coupling to level k+1), which is all the backward sweep needs.
+// The recursion runs in FP64; the stored factors are FP32 (half the bytes for every
+// preconditioner apply), which defines a fixed linear M^{-1} as right preconditioning needs.
 template <class JT>
 __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const int32_t *__restrict__ self_rank,
                                                               const JT *__restrict__ vals,
-                                                              double *__restrict__ fac) {
+                                                              float *__restrict__ fac) {
   const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= m.V) return;
   const int L = m.L;
@@ -111,11 +113,11 @@ __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const 
     Gp[1] = Si[0] * Up[1] + Si[1] * Up[3];
     Gp[2] = Si[2] * Up[0] + Si[3] * Up[2];
     Gp[3] = Si[2] * Up[1] + Si[3] * Up[3];
-    double *Fk = fac + int64_t(k) * 12 * V + v;   // field f of level k at Fk[f V]
+    float *Fk = fac + int64_t(k) * 12 * V + v;   // field f of level k at Fk[f V]
     for (int i = 0; i < 4; ++i) {
-      Fk[i * V] = Si[i];
-      Fk[(4 + i) * V] = Lo[i];
-      Fk[(8 + i) * V] = Gp[i];
+      Fk[i * V] = float(Si[i]);
+      Fk[(4 + i) * V] = float(Lo[i]);
+      Fk[(8 + i) * V] = float(Gp[i]);
     }
   }
 }
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const 
 // factor field are contiguous.  A block's columns are contiguous in r and z (2 (L+1) values
 // each): they are copied through LDS with coalesced loads and stores, and each thread runs
 // its column's two sweeps in place in LDS.
-__global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V, int L, const double *__restrict__ fac,
+__global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V, int L, const float *__restrict__ fac,
                                                                            const double *__restrict__ r,
                                                                            double *__restrict__ z) {
   extern __shared__ double col_sh[];   // [blockDim.x][2 (L + 1)]
@@ -142,16 +144,16 @@ __global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V
     // level's factors are loaded one level ahead.
     double f[8], fn[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) fn[i] = fac[int64_t(i) * Vl + v];
+    for (int i = 0; i < 8; ++i) fn[i] = double(fac[int64_t(i) * Vl + v]);
     double w0 = 0, w1 = 0;
     for (int k = 0; k <= L; ++k) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) f[i] = fn[i];
       double y0 = zv[2 * k], y1 = zv[2 * k + 1];
       if (k < L) {
-        const double *Fn = fac + int64_t(k + 1) * 12 * Vl + v;
+        const float *Fn = fac + int64_t(k + 1) * 12 * Vl + v;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) fn[i] = Fn[i * Vl];
+        for (int i = 0; i < 8; ++i) fn[i] = double(Fn[i * Vl]);
       }
       if (k > 0) {
         y0 -= f[4] * w0 + f[5] * w1;
@@ -166,17 +168,17 @@ __global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V
     double z0 = zv[2 * L], z1 = zv[2 * L + 1];
     double g[4], gn[4];
     {
-      const double *Fk = fac + int64_t(L - 1 >= 0 ? L - 1 : 0) * 12 * Vl + v;
+      const float *Fk = fac + int64_t(L - 1 >= 0 ? L - 1 : 0) * 12 * Vl + v;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) gn[i] = Fk[(8 + i) * Vl];
+      for (int i = 0; i < 4; ++i) gn[i] = double(Fk[(8 + i) * Vl]);
     }
     for (int k = L - 1; k >= 0; --k) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) g[i] = gn[i];
       if (k > 0) {
-        const double *Fn = fac + int64_t(k - 1) * 12 * Vl + v;
+        const float *Fn = fac + int64_t(k - 1) * 12 * Vl + v;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) gn[i] = Fn[(8 + i) * Vl];
+        for (int i = 0; i < 4; ++i) gn[i] = double(Fn[(8 + i) * Vl]);
       }
       const double n0 = zv[2 * k] - (g[0] * z0 + g[1] * z1);
       const double n1 = zv[2 * k + 1] - (g[2] * z0 + g[3] * z1);
@@ -318,7 +320,7 @@ fo_status spmv(const fo_mesh *mesh, const void *vals, int dtype, const double *x
   return FO_OK;
 }
 
-fo_status colblock_factor(const fo_mesh *mesh, const void *vals, int dtype, double *fac, hipStream_t s) {
+fo_status colblock_factor(const fo_mesh *mesh, const void *vals, int dtype, float *fac, hipStream_t s) {
   const MeshView &m = mesh->view;
   const unsigned blocks = unsigned((m.V + 127) / 128);
   if (dtype == FO_F32)
@@ -331,7 +333,7 @@ fo_status colblock_factor(const fo_mesh *mesh, const void *vals, int dtype, doub
   return FO_OK;
 }
 
-fo_status colblock_apply(const fo_mesh *mesh, const double *fac, const double *r, double *z, hipStream_t s) {
+fo_status colblock_apply(const fo_mesh *mesh, const float *fac, const double *r, double *z, hipStream_t s) {
   const MeshView &m = mesh->view;
   // columns per block: the block's columns (2 (L+1) doubles each) stay within 64 KB of LDS
   const size_t col_bytes = size_t(2) * (m.L + 1) * sizeof(double);
