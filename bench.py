@@ -198,7 +198,8 @@ def ensemble_bench(args):
 
 def newton_bench(args):
     """Damped Newton on the ice-sheet mesh from the shallow-ice guess to ||F|| <= 1e-8 ||F(0)||,
-    once with the FP64 and once with the FP32 preconditioner Jacobian; one JSON line each."""
+    once with the FP64 and once with the FP32 preconditioner Jacobian; one JSON line each.
+    --linear-solver pcg takes conjugate gradients instead of GMRES for each Newton step."""
     import torch
 
     from fo_inputs import config1_icesheet
@@ -210,22 +211,25 @@ def newton_bench(args):
     for jdt in ("f64", "f32"):
         opts = M.newton_opts(jac_dtype=jdt)
         ws = torch.empty(M.workspace_bytes(opts), dtype=torch.uint8, device="cuda")
-        M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt, max_newton=1)   # first-call effects
+        lin = args.linear_solver
+        M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt, max_newton=1, linear_solver=lin)   # first call
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep = M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt)
+        rep = M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt, linear_solver=lin)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        print(f"[bench] newton {jdt}: status {rep['status']} its {rep['newton_its']} gmres {rep['lin_its']} "
+        print(f"[bench] newton {jdt}: status {rep['status']} its {rep['newton_its']} {lin} {rep['lin_its']} "
               f"rel {rep['final_rel']:.2e} {wall:.2f} s", file=sys.stderr, flush=True)
         print(json.dumps({
             "metric": "Newton solve wall time, FO-Stokes, shallow-ice start, tol 1e-8",
             "value": wall, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False,
             "dtype": "f64 (Jacobian values " + jdt + ")", "data": "synthetic",
-            "config": {"workload": "icesheet wedge mesh, 2,487,040 wedges, 2,750,000 dofs; GMRES(100) "
-                                   "with vertical-column block-LU preconditioner, lin_rtol 1e-6, <= 500 its/step",
-                       "jacobian_values": jdt},
-            "status": rep["status"], "newton_its": rep["newton_its"], "gmres_its": rep["lin_its"],
+            "config": {"workload": "icesheet wedge mesh, 2,487,040 wedges, 2,750,000 dofs; "
+                                   + ("GMRES(100)" if lin == "gmres" else "conjugate gradients")
+                                   + " with vertical-column block-LU preconditioner, lin_rtol 1e-6, <= 500 its/step",
+                       "jacobian_values": jdt, "linear_solver": lin},
+            "status": rep["status"], "newton_its": rep["newton_its"],
+            ("gmres_its" if lin == "gmres" else "cg_its"): rep["lin_its"],
             "residual_calls": rep["residual_calls"], "jacobian_calls": rep["jacobian_calls"],
             "final_rel": rep["final_rel"], "ms_total_fill": rep["ms_total_fill"],
             "ms_prec_construction": rep["ms_prec_construction"], "ms_linear_solve": rep["ms_linear_solve"],
@@ -245,6 +249,8 @@ def main():
                     help="icesheet: the headline single-mesh line; ensemble: the 64-member batch; "
                          "newton: Newton solves on the ice-sheet mesh with FP64 and FP32 Jacobians")
     ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--linear-solver", choices=["gmres", "pcg"], default="gmres",
+                    help="Newton workload: GMRES (the paper's) or conjugate gradients")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "

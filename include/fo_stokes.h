@@ -117,6 +117,13 @@ fo_status fo_initial_guess_sia(const fo_mesh *mesh, double *U_dev, void *stream)
 
 /* ---- Newton solve (eq. linearsystem: J(U_k) delta = -F(U_k), U_{k+1} = U_k + alpha_k delta) ---- */
 typedef enum { FO_INIT_USER = 0, FO_INIT_SIA = 1 } fo_init;
+/* Linear solver of each Newton step.  FO_LIN_GMRES is the method (GMRES, Sec. 3.1).
+ * FO_LIN_PCG, an option beyond the paper, runs preconditioned conjugate gradients: the
+ * Newton Jacobian is the Hessian of a convex energy and the column block preconditioner is
+ * symmetric positive definite, so CG applies with a few vectors per iteration instead of
+ * the growing Krylov basis; a step whose search direction shows non-positive curvature is
+ * solved again by GMRES. */
+typedef enum { FO_LIN_GMRES = 0, FO_LIN_PCG = 1 } fo_linear_solver;
 
 typedef struct {
   double tol;              /* stop when ||F(U)||_2 <= tol ||F(0)||_2 (default 1e-8) */
@@ -127,6 +134,7 @@ typedef struct {
   int32_t jac_dtype;       /* FO_F64 or FO_F32 Jacobian values for GMRES and preconditioner */
   int32_t max_backtracks;  /* line-search halvings of alpha (10) */
   int32_t init;            /* FO_INIT_USER: U_dev holds the guess; FO_INIT_SIA: shallow-ice guess */
+  int32_t linear_solver;   /* fo_linear_solver (FO_LIN_GMRES); lin_rtol and max_lin apply to both */
 } fo_newton_opts;
 
 typedef struct {

@@ -38,7 +38,7 @@ class NewtonOpts(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_newton", C.c_int32), ("lin_rtol", C.c_double),
         ("gmres_restart", C.c_int32), ("max_lin", C.c_int32), ("jac_dtype", C.c_int32),
-        ("max_backtracks", C.c_int32), ("init", C.c_int32),
+        ("max_backtracks", C.c_int32), ("init", C.c_int32), ("linear_solver", C.c_int32),
     ]
 
 
@@ -59,6 +59,7 @@ class NewtonReport(C.Structure):
 
 
 FO_INIT_USER, FO_INIT_SIA = 0, 1
+FO_LIN_GMRES, FO_LIN_PCG = 0, 1
 
 _lib = None
 

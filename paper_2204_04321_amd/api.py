@@ -128,6 +128,8 @@ class Mesh:
                 v = FO_F64 if v in ("f64", FO_F64) else FO_F32
             elif k == "init":
                 v = {"user": _lib.FO_INIT_USER, "sia": _lib.FO_INIT_SIA}.get(v, v)
+            elif k == "linear_solver":
+                v = {"gmres": _lib.FO_LIN_GMRES, "pcg": _lib.FO_LIN_PCG}.get(v, v)
             setattr(o, k, v)
         return o
 

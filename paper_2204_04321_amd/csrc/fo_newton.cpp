@@ -176,6 +176,64 @@ fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b
   return FO_OK;
 }
 
+// Preconditioned conjugate gradients, x0 = 0, for the symmetric positive definite Newton
+// system (J is the Hessian of a convex energy; M, the column block preconditioner, is SPD).
+// Stops when ||b - J x|| <= lin_rtol ||b|| (the recursively updated residual) or after
+// max_lin iterations.  Sets `breakdown` (returning FO_OK) if a direction has non-positive
+// curvature, which an SPD system cannot produce; the caller then solves by GMRES.
+fo_status pcg(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b, double *x, int64_t &its,
+              double &rel_out, bool &breakdown) {
+  const int64_t n = c.n;
+  double *r = c.dptr(c.L.W), *z = c.dptr(c.L.Z), *p = c.dptr(c.L.T), *q = c.dptr(c.L.V);
+  const float *fac = reinterpret_cast<const float *>(c.ws + c.L.fac);
+  fo_status st;
+  its = 0;
+  breakdown = false;
+  rel_out = 0.0;
+  double bnorm;
+  if ((st = norm2(c, b, bnorm)) != FO_OK) return st;
+  if ((st = launch_fill_zero(x, sizeof(double) * n, c.s)) != FO_OK) return st;   // x = 0
+  if (bnorm == 0.0) return FO_OK;
+  if (!std::isfinite(bnorm)) return fail(FO_ENONFINITE, "pcg: non-finite right-hand side");
+  // a . w and w . w in one reduction
+  auto dot2 = [&](const double *a, const double *w, double &aw, double &ww) -> fo_status {
+    fo_status s2 = multidot(n, a, n, 1, w, c.dptr(c.L.partial), c.dptr(c.L.dots), c.s);
+    if (s2 != FO_OK) return s2;
+    FO_HIP_TRY(hipMemcpyAsync(c.host, c.dptr(c.L.dots), 2 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    FO_HIP_TRY(hipStreamSynchronize(c.s));
+    aw = c.host[0];
+    ww = c.host[1];
+    return FO_OK;
+  };
+  if ((st = axpby(n, 1.0, b, 0.0, r, c.s)) != FO_OK) return st;        // r = b
+  if ((st = colblock_apply(c.m, fac, r, z, c.s)) != FO_OK) return st;  // z = M^-1 r
+  if ((st = axpby(n, 1.0, z, 0.0, p, c.s)) != FO_OK) return st;        // p = z
+  double rz = 0.0, rr = 0.0;
+  if ((st = dot2(z, r, rz, rr)) != FO_OK) return st;
+  while (its < o->max_lin) {
+    if ((st = spmv(c.m, Jv, o->jac_dtype, p, q, c.s)) != FO_OK) return st;   // q = J p
+    double pq = 0.0, qq = 0.0;
+    if ((st = dot2(p, q, pq, qq)) != FO_OK) return st;
+    if (!std::isfinite(pq) || !std::isfinite(rz)) return fail(FO_ENONFINITE, "pcg: non-finite Krylov vector");
+    if (!(pq > 0.0) || !(rz > 0.0)) {
+      breakdown = true;
+      return FO_OK;
+    }
+    const double alpha = rz / pq;
+    if ((st = axpby(n, alpha, p, 1.0, x, c.s)) != FO_OK) return st;    // x += alpha p
+    if ((st = axpby(n, -alpha, q, 1.0, r, c.s)) != FO_OK) return st;   // r -= alpha q
+    if ((st = colblock_apply(c.m, fac, r, z, c.s)) != FO_OK) return st;
+    double rz1 = 0.0;
+    if ((st = dot2(z, r, rz1, rr)) != FO_OK) return st;
+    ++its;
+    rel_out = std::sqrt(rr) / bnorm;
+    if (rel_out <= o->lin_rtol) break;
+    if ((st = xpay(n, z, rz1 / rz, p, p, c.s)) != FO_OK) return st;   // p = z + beta p
+    rz = rz1;
+  }
+  return FO_OK;
+}
+
 }  // namespace
 }  // namespace fo
 
@@ -191,6 +249,7 @@ extern "C" void fo_newton_default_opts(fo_newton_opts *o) {
   o->jac_dtype = FO_F64;
   o->max_backtracks = 10;
   o->init = FO_INIT_USER;
+  o->linear_solver = FO_LIN_GMRES;
 }
 
 extern "C" size_t fo_newton_workspace_bytes(const fo_mesh *m, const fo_newton_opts *o) {
@@ -203,7 +262,8 @@ extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newto
   if (!m || !U || !o || !rep || !ws) return fail(FO_EINVAL, "fo_newton_solve: NULL argument");
   if (o->gmres_restart < 1 || o->gmres_restart > 500 || o->max_lin < 1 || o->max_newton < 0 ||
       !(o->tol > 0) || !(o->lin_rtol > 0) || o->max_backtracks < 0 ||
-      (o->jac_dtype != FO_F64 && o->jac_dtype != FO_F32) || (o->init != FO_INIT_USER && o->init != FO_INIT_SIA))
+      (o->jac_dtype != FO_F64 && o->jac_dtype != FO_F32) || (o->init != FO_INIT_USER && o->init != FO_INIT_SIA) ||
+      (o->linear_solver != FO_LIN_GMRES && o->linear_solver != FO_LIN_PCG))
     return fail(FO_EINVAL, "fo_newton_solve: bad options");
   if ((reinterpret_cast<uintptr_t>(U) & 15) || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(FO_EINVAL, "fo_newton_solve: U must be 16-byte and workspace 256-byte aligned");
@@ -264,7 +324,13 @@ extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newto
     if ((st = axpby(c.n, -1.0, R, 0.0, Rt, c.s)) != FO_OK) return st;
     int64_t lits = 0;
     double lrel = 0.0;
-    if ((st = gmres(c, o, Jv, Rt, dU, lits, lrel)) != FO_OK) return st;
+    bool breakdown = o->linear_solver != FO_LIN_PCG;
+    if (!breakdown && (st = pcg(c, o, Jv, Rt, dU, lits, lrel, breakdown)) != FO_OK) return st;
+    if (breakdown) {   // GMRES: the default, or PCG met non-positive curvature
+      int64_t g_its = 0;
+      if ((st = gmres(c, o, Jv, Rt, dU, g_its, lrel)) != FO_OK) return st;
+      lits += g_its;
+    }
     rep->ms_linear_solve += ms_since(t0);
     rep->lin_its += lits;
     // backtracking line search

@@ -41,6 +41,7 @@ int main(void) {
   if (st != FO_EINVAL) return 1;
   fo_newton_opts o;
   fo_newton_default_opts(&o);
-  printf("default Newton tol %g, restart %d\n", o.tol, (int)o.gmres_restart);
+  printf("default Newton tol %g, restart %d, linear solver %d, opts size %d\n", o.tol, (int)o.gmres_restart,
+         (int)o.linear_solver, (int)sizeof o);
   return 0;
 }

@@ -144,3 +144,9 @@ def test_plain_c_caller(tmp_path):
     p = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert p.returncode == 0, p.stdout + p.stderr
     assert "degenerate" in p.stdout
+    # the binding's option struct has the C layout and defaults (GMRES, the paper's solver)
+    from paper_2204_04321_amd import _lib
+    o = _lib.NewtonOpts()
+    _lib.lib().fo_newton_default_opts(ctypes.byref(o))
+    assert o.linear_solver == _lib.FO_LIN_GMRES and o.gmres_restart == 100
+    assert f"linear solver 0, opts size {ctypes.sizeof(_lib.NewtonOpts)}" in p.stdout

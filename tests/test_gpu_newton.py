@@ -46,6 +46,21 @@ def test_newton_matches_oracle_solution(cap, jdt):
     assert np.abs(Ug - U_ref).max() <= 1e-5 * np.abs(U_ref).max()
 
 
+@pytest.mark.parametrize("jdt", ["f64", "f32"])
+def test_newton_pcg_matches_oracle_solution(cap, jdt):
+    """The conjugate-gradient option (the Newton Jacobian is symmetric positive definite)
+    reaches the same solution as the oracle's direct-solve Newton."""
+    m, U_ref, M = cap
+    U = to_dev(solve.sia_guess(m))
+    rep = M.newton_solve(U, tol=1e-8, jac_dtype=jdt, linear_solver="pcg")
+    print(f"\n[newton pcg {jdt}] its {rep['newton_its']} cg {rep['lin_its']} res {rep['final_rel']:.2e}")
+    assert rep["status"] == 0, rep
+    Ug = U.cpu().numpy()
+    f0 = np.linalg.norm(fo.residual(m, np.zeros_like(Ug)))
+    assert np.linalg.norm(fo.residual(m, Ug)) <= 1.01e-8 * f0
+    assert np.abs(Ug - U_ref).max() <= 1e-5 * np.abs(U_ref).max()
+
+
 def test_newton_sia_init_and_slab():
     m, U0 = config0_slab()
     M = gpu_mesh(m)
@@ -77,12 +92,19 @@ def test_newton_nonfinite_guess_is_reported(cap):
     assert rep["status"] == -5
 
 
+def _lib_einval():
+    from paper_2204_04321_amd import _lib
+    return _lib.FO_EINVAL
+
+
 def test_newton_rejects_bad_options(cap):
     from paper_2204_04321_amd import FoError
     m, _, M = cap
     U = to_dev(solve.sia_guess(m))
     with pytest.raises(ValueError):
         M.newton_solve(U, gmres_restart=0)
+    rep = M.newton_solve(U, linear_solver=7)
+    assert rep["status"] == _lib_einval() and "bad options" in rep["message"]
 
 
 @pytest.mark.parametrize("n_glen, A, tol_ref", [(1.0, 2e-13, 1e-9), (4.0, 1e-21, 1e-11)])
