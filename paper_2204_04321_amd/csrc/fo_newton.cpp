@@ -8,6 +8,7 @@
 // Total Fill (all assembly calls), Preconditioner Construction, Linear Solve, Total Solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -44,7 +45,7 @@ Layout layout(const fo_mesh *m, const fo_newton_opts *o) {
   L.fac = take(4 * size_t(m->view.V) * size_t(m->view.L + 1) * 12);
   L.V = take(8 * n * size_t(mres + 1));
   L.partial = take(8 * size_t(multidot_blocks(int64_t(n))) * size_t(mres + 2));
-  L.dots = take(8 * size_t(mres + 2));
+  L.dots = take(8 * std::max(size_t(mres + 2), size_t(8)));   // GMRES: h and norms; CG: 6 scalars
   L.total = off;
   return L;
 }
@@ -195,41 +196,44 @@ fo_status pcg(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b, 
   if ((st = launch_fill_zero(x, sizeof(double) * n, c.s)) != FO_OK) return st;   // x = 0
   if (bnorm == 0.0) return FO_OK;
   if (!std::isfinite(bnorm)) return fail(FO_ENONFINITE, "pcg: non-finite right-hand side");
-  // a . w and w . w in one reduction
-  auto dot2 = [&](const double *a, const double *w, double &aw, double &ww) -> fo_status {
-    fo_status s2 = multidot(n, a, n, 1, w, c.dptr(c.L.partial), c.dptr(c.L.dots), c.s);
-    if (s2 != FO_OK) return s2;
-    FO_HIP_TRY(hipMemcpyAsync(c.host, c.dptr(c.L.dots), 2 * sizeof(double), hipMemcpyDeviceToHost, c.s));
-    FO_HIP_TRY(hipStreamSynchronize(c.s));
-    aw = c.host[0];
-    ww = c.host[1];
-    return FO_OK;
-  };
+  // device scalars: d[0] = p . q (d[1] = q . q, unused), d[2 + 2 s] = r . z and
+  // d[3 + 2 s] = r . r of the two alternating slots s; one host synchronisation per iteration
+  double *d = c.dptr(c.L.dots);
+  double *part = c.dptr(c.L.partial);
   if ((st = axpby(n, 1.0, b, 0.0, r, c.s)) != FO_OK) return st;        // r = b
   if ((st = colblock_apply(c.m, fac, r, z, c.s)) != FO_OK) return st;  // z = M^-1 r
   if ((st = axpby(n, 1.0, z, 0.0, p, c.s)) != FO_OK) return st;        // p = z
-  double rz = 0.0, rr = 0.0;
-  if ((st = dot2(z, r, rz, rr)) != FO_OK) return st;
+  if ((st = multidot(n, z, n, 1, r, part, d + 2, c.s)) != FO_OK) return st;
+  FO_HIP_TRY(hipMemcpyAsync(c.host, d + 2, sizeof(double), hipMemcpyDeviceToHost, c.s));
+  FO_HIP_TRY(hipStreamSynchronize(c.s));
+  double rz = c.host[0];
+  int slot = 0;
   while (its < o->max_lin) {
-    if ((st = spmv(c.m, Jv, o->jac_dtype, p, q, c.s)) != FO_OK) return st;   // q = J p
-    double pq = 0.0, qq = 0.0;
-    if ((st = dot2(p, q, pq, qq)) != FO_OK) return st;
-    if (!std::isfinite(pq) || !std::isfinite(rz)) return fail(FO_ENONFINITE, "pcg: non-finite Krylov vector");
-    if (!(pq > 0.0) || !(rz > 0.0)) {
+    if (!std::isfinite(rz)) return fail(FO_ENONFINITE, "pcg: non-finite Krylov vector");
+    if (!(rz > 0.0)) {
       breakdown = true;
       return FO_OK;
     }
-    const double alpha = rz / pq;
-    if ((st = axpby(n, alpha, p, 1.0, x, c.s)) != FO_OK) return st;    // x += alpha p
-    if ((st = axpby(n, -alpha, q, 1.0, r, c.s)) != FO_OK) return st;   // r -= alpha q
-    if ((st = colblock_apply(c.m, fac, r, z, c.s)) != FO_OK) return st;
-    double rz1 = 0.0;
-    if ((st = dot2(z, r, rz1, rr)) != FO_OK) return st;
+    if ((st = spmv(c.m, Jv, o->jac_dtype, p, q, c.s)) != FO_OK) return st;              // q = J p
+    if ((st = multidot(n, p, n, 1, q, part, d, c.s)) != FO_OK) return st;               // p . q
+    if ((st = cg_step(n, d + 2 + 2 * slot, d, p, q, x, r, c.s)) != FO_OK) return st;    // x, r
+    if ((st = colblock_apply(c.m, fac, r, z, c.s)) != FO_OK) return st;                 // z = M^-1 r
+    const int nxt = slot ^ 1;
+    if ((st = multidot(n, z, n, 1, r, part, d + 2 + 2 * nxt, c.s)) != FO_OK) return st;  // r . z, r . r
+    FO_HIP_TRY(hipMemcpyAsync(c.host, d, 6 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    FO_HIP_TRY(hipStreamSynchronize(c.s));
+    const double pq = c.host[0], rz1 = c.host[2 + 2 * nxt], rr = c.host[3 + 2 * nxt];
+    if (!std::isfinite(pq)) return fail(FO_ENONFINITE, "pcg: non-finite curvature");
+    if (!(pq > 0.0)) {   // this step's update of x used a meaningless length: GMRES redoes it
+      breakdown = true;
+      return FO_OK;
+    }
     ++its;
     rel_out = std::sqrt(rr) / bnorm;
     if (rel_out <= o->lin_rtol) break;
     if ((st = xpay(n, z, rz1 / rz, p, p, c.s)) != FO_OK) return st;   // p = z + beta p
     rz = rz1;
+    slot = nxt;
   }
   return FO_OK;
 }

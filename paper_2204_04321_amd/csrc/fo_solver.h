@@ -15,6 +15,9 @@ fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double 
 // w += sign * sum_i h_i V_i (n and ld even, FO_EINVAL otherwise)
 fo_status multiaxpy(int64_t n, const double *V, int64_t ld, int nv, const double *h, double *w, double sign,
                     hipStream_t s);
+// x += alpha p, r -= alpha q with alpha = num[0] / den[0] read on the device
+fo_status cg_step(int64_t n, const double *num, const double *den, const double *p, const double *q, double *x,
+                  double *r, hipStream_t s);
 fo_status axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 fo_status xpay(int64_t n, const double *x, double a, const double *y, double *z, hipStream_t s);
 }  // namespace fo

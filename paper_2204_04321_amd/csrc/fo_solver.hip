@@ -283,6 +283,21 @@ __global__ __launch_bounds__(256) void multiaxpy_kernel(int64_t n2, const double
   }
 }
 
+// conjugate-gradient step with the step length formed on the device:
+// alpha = num[0] / den[0], x += alpha p, r -= alpha q
+__global__ __launch_bounds__(256) void cg_step_kernel(int64_t n, const double *__restrict__ num,
+                                                      const double *__restrict__ den,
+                                                      const double *__restrict__ p,
+                                                      const double *__restrict__ q, double *__restrict__ x,
+                                                      double *__restrict__ r) {
+  const double alpha = num[0] / den[0];
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+
 // y = a x + b y
 __global__ __launch_bounds__(256) void axpby_kernel(int64_t n, double a, const double *__restrict__ x, double b,
                                                     double *__restrict__ y) {
@@ -368,6 +383,13 @@ fo_status multiaxpy(int64_t n, const double *V, int64_t ld, int nv, const double
   hipLaunchKernelGGL(multiaxpy_kernel, dim3(unsigned(g < 2048 ? (g > 0 ? g : 1) : 2048)), dim3(256), 0, s, n / 2, V,
                      ld, nv, h, w, sign);
   FO_LAUNCH_CHECK("multiaxpy_kernel");
+  return FO_OK;
+}
+
+fo_status cg_step(int64_t n, const double *num, const double *den, const double *p, const double *q, double *x,
+                  double *r, hipStream_t s) {
+  hipLaunchKernelGGL(cg_step_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, num, den, p, q, x, r);
+  FO_LAUNCH_CHECK("cg_step_kernel");
   return FO_OK;
 }
 
