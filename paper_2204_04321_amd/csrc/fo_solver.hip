@@ -50,6 +50,35 @@ __global__ __launch_bounds__(256) void spmv_kernel(int V, int L, const int64_t *
     const int klo = k > 0 ? k - 1 : 0;
     const JT *row = vals + colptr[v] + int64_t(4) * D * cumlev(k);
     const int len = 2 * nl * D;
+    if constexpr (sizeof(JT) == 4) {
+      // FP32 values: two column pairs per lane, one 16-byte load per row (the second row
+      // starts 2 nl D entries later, so its loads are only 8-byte aligned)
+      for (int q = 2 * sub; q + 1 < nl * D; q += 2 * SPMV_LANES) {
+        const int r0 = nl == 3 ? (q * 43691) >> 17 : q >> 1, r1 = nl == 3 ? ((q + 1) * 43691) >> 17 : (q + 1) >> 1;
+        const int64_t c0 = 2 * (int64_t(nbr_idx[nb + r0]) * (L + 1) + klo + (q - r0 * nl));
+        const int64_t c1 = 2 * (int64_t(nbr_idx[nb + r1]) * (L + 1) + klo + (q + 1 - r1 * nl));
+        const double2 x0 = *reinterpret_cast<const double2 *>(x + c0);
+        const double2 x1 = *reinterpret_cast<const double2 *>(x + c1);
+        float4 v0, v1;
+        __builtin_memcpy(&v0, row + 2 * q, sizeof v0);
+        __builtin_memcpy(&v1, row + len + 2 * q, sizeof v1);
+        a0 = fma(double(v0.x), x0.x, fma(double(v0.y), x0.y, a0));
+        a0 = fma(double(v0.z), x1.x, fma(double(v0.w), x1.y, a0));
+        a1 = fma(double(v1.x), x0.x, fma(double(v1.y), x0.y, a1));
+        a1 = fma(double(v1.z), x1.x, fma(double(v1.w), x1.y, a1));
+      }
+      if ((nl * D) & 1) {   // the last column pair of an odd count
+        const int q = nl * D - 1;
+        if (sub == (q >> 1) % SPMV_LANES) {
+          const int r = nl == 3 ? (q * 43691) >> 17 : q >> 1;
+          const int64_t col = 2 * (int64_t(nbr_idx[nb + r]) * (L + 1) + klo + (q - r * nl));
+          const double2 xv = *reinterpret_cast<const double2 *>(x + col);
+          const T2 v0 = *reinterpret_cast<const T2 *>(row + 2 * q), v1 = *reinterpret_cast<const T2 *>(row + len + 2 * q);
+          a0 = fma(double(v0.x), xv.x, fma(double(v0.y), xv.y, a0));
+          a1 = fma(double(v1.x), xv.x, fma(double(v1.y), xv.y, a1));
+        }
+      }
+    } else
     for (int q = sub; q < nl * D; q += SPMV_LANES) {
       const int r = nl == 3 ? (q * 43691) >> 17 : q >> 1;   // q / nl, exact for q < 65536
       const int lev = q - r * nl;
