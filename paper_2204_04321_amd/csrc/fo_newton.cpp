@@ -44,7 +44,8 @@ Layout layout(const fo_mesh *m, const fo_newton_opts *o) {
   L.T = take(8 * n);
   L.fac = take(4 * size_t(m->view.V) * size_t(m->view.L + 1) * 12);
   L.V = take(8 * n * size_t(mres + 1));
-  L.partial = take(8 * size_t(multidot_blocks(int64_t(n))) * size_t(mres + 2));
+  L.partial = take(8 * std::max(size_t(multidot_blocks(int64_t(n))) * size_t(mres + 2),
+                                 2 * size_t(dot2_blocks(int64_t(n)))));
   L.dots = take(8 * std::max(size_t(mres + 2), size_t(8)));   // GMRES: h and norms; CG: 6 scalars
   L.total = off;
   return L;
@@ -203,7 +204,7 @@ fo_status pcg(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b, 
   if ((st = axpby(n, 1.0, b, 0.0, r, c.s)) != FO_OK) return st;        // r = b
   if ((st = colblock_apply(c.m, fac, r, z, c.s)) != FO_OK) return st;  // z = M^-1 r
   if ((st = axpby(n, 1.0, z, 0.0, p, c.s)) != FO_OK) return st;        // p = z
-  if ((st = multidot(n, z, n, 1, r, part, d + 2, c.s)) != FO_OK) return st;
+  if ((st = dot2(n, z, r, part, d + 2, c.s)) != FO_OK) return st;
   FO_HIP_TRY(hipMemcpyAsync(c.host, d + 2, sizeof(double), hipMemcpyDeviceToHost, c.s));
   FO_HIP_TRY(hipStreamSynchronize(c.s));
   double rz = c.host[0];
@@ -215,11 +216,11 @@ fo_status pcg(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b, 
       return FO_OK;
     }
     if ((st = spmv(c.m, Jv, o->jac_dtype, p, q, c.s)) != FO_OK) return st;              // q = J p
-    if ((st = multidot(n, p, n, 1, q, part, d, c.s)) != FO_OK) return st;               // p . q
+    if ((st = dot2(n, p, q, part, d, c.s)) != FO_OK) return st;                         // p . q
     if ((st = cg_step(n, d + 2 + 2 * slot, d, p, q, x, r, c.s)) != FO_OK) return st;    // x, r
     if ((st = colblock_apply(c.m, fac, r, z, c.s)) != FO_OK) return st;                 // z = M^-1 r
     const int nxt = slot ^ 1;
-    if ((st = multidot(n, z, n, 1, r, part, d + 2 + 2 * nxt, c.s)) != FO_OK) return st;  // r . z, r . r
+    if ((st = dot2(n, z, r, part, d + 2 + 2 * nxt, c.s)) != FO_OK) return st;            // r . z, r . r
     FO_HIP_TRY(hipMemcpyAsync(c.host, d, 6 * sizeof(double), hipMemcpyDeviceToHost, c.s));
     FO_HIP_TRY(hipStreamSynchronize(c.s));
     const double pq = c.host[0], rz1 = c.host[2 + 2 * nxt], rr = c.host[3 + 2 * nxt];

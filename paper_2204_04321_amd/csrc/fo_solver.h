@@ -12,6 +12,9 @@ int multidot_blocks(int64_t n);
 // n and ld even, FO_EINVAL otherwise)
 fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double *w, double *partial,
                    double *out, hipStream_t s);
+int dot2_blocks(int64_t n);
+// out[0] = a . w, out[1] = w . w (partial: 2 dot2_blocks(n) doubles; n even, FO_EINVAL otherwise)
+fo_status dot2(int64_t n, const double *a, const double *w, double *partial, double *out, hipStream_t s);
 // w += sign * sum_i h_i V_i (n and ld even, FO_EINVAL otherwise)
 fo_status multiaxpy(int64_t n, const double *V, int64_t ld, int nv, const double *h, double *w, double sign,
                     hipStream_t s);

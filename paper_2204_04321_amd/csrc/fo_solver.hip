@@ -275,6 +275,37 @@ __global__ __launch_bounds__(RED_BLOCK) void multidot_kernel(int64_t n2, const d
   }
 }
 
+// partial[2 b] = sum over block b's entries of a . w, partial[2 b + 1] of w . w; two
+// consecutive entries per lane, grid-stride
+__global__ __launch_bounds__(RED_BLOCK) void dot2_kernel(int64_t n2, const double *__restrict__ a,
+                                                         const double *__restrict__ w,
+                                                         double *__restrict__ partial) {
+  __shared__ double red[2][RED_BLOCK / 64];
+  const int64_t stride = int64_t(gridDim.x) * RED_BLOCK;
+  const double2 *a2 = reinterpret_cast<const double2 *>(a);
+  const double2 *w2 = reinterpret_cast<const double2 *>(w);
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t p = int64_t(blockIdx.x) * RED_BLOCK + threadIdx.x; p < n2; p += stride) {
+    const double2 x = a2[p], y = w2[p];
+    s0 = fma(x.x, y.x, fma(x.y, y.y, s0));
+    s1 = fma(y.x, y.x, fma(y.y, y.y, s1));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off);
+    s1 += __shfl_xor(s1, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s0;
+    red[1][threadIdx.x >> 6] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int q = 0; q < RED_BLOCK / 64; ++q) t += red[threadIdx.x][q];
+    partial[2 * int64_t(blockIdx.x) + threadIdx.x] = t;
+  }
+}
+
 // out[i] = sum_b partial[b * stride + i], fixed order
 __global__ void reduce_partials_kernel(int nb, int stride, const double *__restrict__ partial,
                                        double *__restrict__ out) {
@@ -401,6 +432,21 @@ fo_status multidot(int64_t n, const double *V, int64_t ld, int nv, const double 
   hipLaunchKernelGGL(multidot_kernel, dim3(nb), dim3(RED_BLOCK), 0, s, n / 2, V, ld, nv, w, partial);
   FO_LAUNCH_CHECK("multidot_kernel");
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(nv + 1), dim3(256), 0, s, nb, nv + 1, partial, out);
+  FO_LAUNCH_CHECK("reduce_partials_kernel");
+  return FO_OK;
+}
+
+int dot2_blocks(int64_t n) {
+  const int64_t g = (n / 2 + 4 * RED_BLOCK - 1) / (4 * RED_BLOCK);
+  return int(g < 2048 ? (g > 0 ? g : 1) : 2048);
+}
+
+fo_status dot2(int64_t n, const double *a, const double *w, double *partial, double *out, hipStream_t s) {
+  if (n & 1) return fail(FO_EINVAL, "dot2: vector length must be even");
+  const int nb = dot2_blocks(n);
+  hipLaunchKernelGGL(dot2_kernel, dim3(nb), dim3(RED_BLOCK), 0, s, n / 2, a, w, partial);
+  FO_LAUNCH_CHECK("dot2_kernel");
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, s, nb, 2, partial, out);
   FO_LAUNCH_CHECK("reduce_partials_kernel");
   return FO_OK;
 }
