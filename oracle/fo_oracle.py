@@ -304,12 +304,10 @@ def residual(mesh, U, **kw):
     return assemble(mesh, U, want_jac=False, **kw)[0]
 
 
-def abs_scales(mesh, U, picard=False, chunk=20000, cells=None):
-    """Row scales for rounding-level parity: sum over cells and quadrature points of the
-    absolute values of the terms summed into R_i, and max_j of the same for J_ij (optionally
-    from a subset of cells: exact for rows whose cells are all included).  Any summation
-    order of the same terms differs from another by at most a small multiple of the unit
-    roundoff times these sums."""
+def _row_sums_and_matrix(mesh, U, picard, chunk, cells, absolute):
+    """Sum over cells of |R_e,i| and the CSR matrix of sum over cells of |J_e,ij|, where
+    R_e, J_e are the element arrays (absolute=False) or, per element, the sums of the
+    absolute values of their quadrature-point terms (absolute=True)."""
     ref = RefElement(mesh.elem)
     xyz = node_xyz(mesh)
     nd = mesh.n_dofs
@@ -318,7 +316,7 @@ def abs_scales(mesh, U, picard=False, chunk=20000, cells=None):
     all_cells = np.arange(mesh.n_cells) if cells is None else np.asarray(cells)
     for ch in _chunks(all_cells.shape[0], chunk):
         ids = all_cells[ch]
-        Re, Je, nodes = element_arrays(mesh, ids, U, ref, True, picard, xyz, absolute=True)
+        Re, Je, nodes = element_arrays(mesh, ids, U, ref, True, picard, xyz, absolute=absolute)
         dofs = (2 * nodes[:, :, None] + np.arange(2)[None, None, :]).reshape(ids.shape[0], -1)
         rs += np.bincount(dofs.ravel(), weights=np.abs(Re).reshape(-1), minlength=nd)
         m = dofs.shape[1]
@@ -326,8 +324,33 @@ def abs_scales(mesh, U, picard=False, chunk=20000, cells=None):
         cols = np.tile(dofs, (1, m)).ravel()
         Jc = sp.coo_matrix((np.abs(Je).reshape(-1), (rows, cols)), shape=(nd, nd)).tocsr()
         Jabs = Jc if Jabs is None else Jabs + Jc
+    Jabs.sum_duplicates()
+    Jabs.sort_indices()
+    return rs, Jabs
+
+
+def abs_terms(mesh, U, picard=False, chunk=20000, cells=None):
+    """Per-entry scales: S^R_i = sum over cells and quadrature points of the absolute values
+    of the terms summed into R_i, and the CSR matrix S^J_ij of the same for J_ij."""
+    return _row_sums_and_matrix(mesh, U, picard, chunk, cells, absolute=True)
+
+
+def abs_scales(mesh, U, picard=False, chunk=20000, cells=None):
+    """Row scales for rounding-level parity: S^R_i (abs_terms) and max_j S^J_ij
+    (optionally from a subset of cells: exact for rows whose cells are all included).  Any
+    summation order of the same terms differs from another by at most a small multiple of
+    the unit roundoff times these sums."""
+    rs, Jabs = abs_terms(mesh, U, picard, chunk, cells)
     jrow = np.asarray(Jabs.max(axis=1).todense()).ravel()
     return rs, jrow
+
+
+def element_scales(mesh, U, picard=False, chunk=20000, cells=None):
+    """Element-level row scales: sum_e |R_e,i| and max_j sum_e |J_e,ij| over the element
+    residuals and Jacobians.  They lie below the per-term scales of abs_scales wherever the
+    terms inside one element cancel."""
+    rs, Je = _row_sums_and_matrix(mesh, U, picard, chunk, cells, absolute=False)
+    return rs, np.asarray(Je.max(axis=1).todense()).ravel()
 
 
 def cells_touching_nodes(mesh, nodes_sel: np.ndarray) -> np.ndarray:

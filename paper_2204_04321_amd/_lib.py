@@ -98,15 +98,6 @@ def _declare(lib):
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    for name, (res, args) in EXTRA_SIGNATURES.items():
-        if hasattr(lib, name):
-            f = getattr(lib, name)
-            f.restype = res
-            f.argtypes = args
-
-
-# entry points added by later parts of the library (declared when present)
-EXTRA_SIGNATURES: dict = {}
 
 
 def lib():

@@ -6,7 +6,7 @@
 // that block from J and factoring it by block LU without pivoting, one vertical line
 // per thread, follows the batched per-line solve the paper uses inside its
 // semicoarsening multigrid (arXiv:2204.04321 Sec. 4.4); here it is used directly as
-// a block-Jacobi preconditioner for GMRES (Sec. 3.3 names GMRES as the Krylov method).
+// a block-Jacobi preconditioner for GMRES (Sec. 3.1 names GMRES as the Krylov method).
 #include <hip/hip_runtime.h>
 
 #include "fo_internal.h"

@@ -29,13 +29,33 @@ def gpu_residual(M, U):
     return R.cpu().numpy()
 
 
-def row_scaled_errors(R_gpu, J_gpu, R_ref, J_ref, rscale, jscale):
-    """max_i |dR_i| / sum_e |R_e,i| and max_ij |dJ_ij| / max_j sum_e |J_e,ij|."""
-    er = np.max(np.abs(R_gpu - R_ref) / np.maximum(rscale, 1e-300))
+def _row_max_abs(D):
+    """max_j |D_ij| per row of a CSR matrix (0 for empty rows)."""
+    out = np.zeros(D.shape[0])
+    if D.nnz:
+        rows = np.repeat(np.arange(D.shape[0]), np.diff(D.indptr))
+        np.maximum.at(out, rows, np.abs(D.data))
+    return out
+
+
+def parity_errors(R_gpu, J_gpu, R_ref, J_ref, term_scales, elem_scales):
+    """Errors of a GPU residual / Jacobian against the oracle on three scales:
+    'term'  - row-scaled by the per-term scale (|dR_i| / S^R_i, max_j |dJ_ij| / max_j S^J_ij),
+    'elem'  - row-scaled by the element-level scale (sum_e |R_e,i|, max_j sum_e |J_e,ij|),
+    'plain' - norm-wise, ||dR||_inf / ||R||_inf and max |dJ| / max |J|.
+    Returns {scale: (err_R, err_J)} and, under 'worst_elem', the rows where the element-level
+    errors peak."""
+    dR = np.abs(R_gpu - R_ref)
     D = (J_gpu - J_ref).tocsr()
     D.sum_duplicates()
-    if D.nnz == 0:
-        return er, 0.0
-    rows = np.repeat(np.arange(D.shape[0]), np.diff(D.indptr))
-    ej = np.max(np.abs(D.data) / np.maximum(jscale[rows], 1e-300))
-    return er, ej
+    dJ = _row_max_abs(D)
+    out = {}
+    for name, (rs, js) in (("term", term_scales), ("elem", elem_scales)):
+        er = dR / np.maximum(rs, 1e-300)
+        ej = dJ / np.maximum(js, 1e-300)
+        out[name] = (float(er.max()), float(ej.max()))
+        if name == "elem":
+            out["worst_elem"] = (int(er.argmax()), int(ej.argmax()))
+    out["plain"] = (float(dR.max() / np.abs(R_ref).max()),
+                    float(dJ.max() / np.abs(J_ref.data).max()) if J_ref is not None else 0.0)
+    return out

@@ -1,9 +1,15 @@
 """GPU parity of the HIP assembly path against the FP64 oracle (through the C ABI).
 
-Bar: FP64 residual and Jacobian within 1e-12 of the oracle, row-scaled by the
-assembled absolute element contributions (|dR_i| <= 1e-12 sum_e |R_e,i|,
-|dJ_ij| <= 1e-12 max_j sum_e |J_e,ij|); FP32 Jacobian values within 1e-5 on
-the same scale; integer pattern bit-exact.
+Bars, each asserted (FP64):
+  * row-scaled by the per-term scale S (the sum of the absolute values of every
+    quadrature-point term summed into the entry; it bounds the rounding error of any
+    summation order): |dR_i| <= 1e-12 S^R_i, |dJ_ij| <= 1e-12 max_j S^J_ij;
+  * row-scaled by the element-level scale: |dR_i| <= TOL64_ELEM sum_e |R_e,i|,
+    |dJ_ij| <= TOL64_ELEM max_j sum_e |J_e,ij| (looser than S where the terms of one
+    element cancel);
+  * norm-wise: ||dR||_inf <= 1e-12 ||R||_inf, max |dJ| <= 1e-12 max |J|.
+FP32 Jacobian values: 1e-5 on the per-term and element-level scales, 1e-6 norm-wise.
+Integer pattern bit-exact.
 """
 import numpy as np
 import pytest
@@ -15,12 +21,14 @@ from fo_inputs.meshgen import ExtrudedMesh, _dome_fields, dome_velocity, ellipse
 from oracle import fo_oracle as fo
 from oracle import solve
 
-from gpu_util import gpu_jacobian, gpu_mesh, gpu_residual, row_scaled_errors, to_dev
+from gpu_util import gpu_jacobian, gpu_mesh, gpu_residual, parity_errors, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-12
-TOL32 = 1e-5
+TOL64 = 1e-12        # per-term row scale and norm-wise
+TOL64_ELEM = 1e-12   # element-level row scale
+TOL32 = 1e-5         # FP32 Jacobian, row scales
+TOL32_PLAIN = 1e-6   # FP32 Jacobian, norm-wise
 
 
 def _small_ellipse(seed=5, n_points=300, L=7):
@@ -109,16 +117,23 @@ def test_pattern_matches_oracle(case):
     np.testing.assert_array_equal(colidx.cpu().numpy().astype(np.int64), ci)
 
 
+def _report(tag, e):
+    print(f"[{tag}] R: term {e['term'][0]:.2e} elem {e['elem'][0]:.2e} plain {e['plain'][0]:.2e} | "
+          f"J: term {e['term'][1]:.2e} elem {e['elem'][1]:.2e} plain {e['plain'][1]:.2e} | "
+          f"worst elem rows R {e['worst_elem'][0]} J {e['worst_elem'][1]}")
+
+
 @pytest.mark.parametrize("kind", ["newton", "picard"])
 def test_jacobian_f64_parity(case, kind):
     name, m, U, M = case
+    pic = kind == "picard"
     R, J = gpu_jacobian(M, U, "f64", kind)
-    Ro, Jo = fo.assemble(m, U, picard=(kind == "picard"))
-    rs, js = fo.abs_scales(m, U, picard=(kind == "picard"))
-    er, ej = row_scaled_errors(R, J, Ro, Jo, rs, js)
-    print(f"[{name}/{kind}] row-scaled err R {er:.2e} J {ej:.2e}; "
-          f"plain |dJ|/|J| {abs(J - Jo).max() / abs(Jo).max():.2e}")
-    assert er <= TOL64 and ej <= TOL64
+    Ro, Jo = fo.assemble(m, U, picard=pic)
+    e = parity_errors(R, J, Ro, Jo, fo.abs_scales(m, U, picard=pic), fo.element_scales(m, U, picard=pic))
+    _report(f"{name}/{kind}", e)
+    assert max(e["term"]) <= TOL64
+    assert max(e["elem"]) <= TOL64_ELEM
+    assert max(e["plain"]) <= TOL64
 
 
 def test_residual_f64_parity(case):
@@ -126,19 +141,22 @@ def test_residual_f64_parity(case):
     R = gpu_residual(M, U)
     Ro = fo.residual(m, U)
     rs, _ = fo.abs_scales(m, U)
-    er = np.max(np.abs(R - Ro) / rs)
-    assert er <= TOL64
+    er_, _ = fo.element_scales(m, U)
+    d = np.abs(R - Ro)
+    term, elem, plain = (d / rs).max(), (d / er_).max(), d.max() / np.abs(Ro).max()
+    print(f"[{name}/residual] term {term:.2e} elem {elem:.2e} plain {plain:.2e}")
+    assert term <= TOL64 and elem <= TOL64_ELEM and plain <= TOL64
 
 
 def test_jacobian_f32_bound(case):
     name, m, U, M = case
     R, J = gpu_jacobian(M, U, "f32", "newton")
     Ro, Jo = fo.assemble(m, U)
-    rs, js = fo.abs_scales(m, U)
-    er, ej = row_scaled_errors(R, J, Ro, Jo, rs, js)
-    print(f"[{name}/f32] residual (FP64) err {er:.2e}, FP32 J row-scaled err {ej:.2e}")
-    assert er <= TOL64      # residual stays FP64
-    assert ej <= TOL32
+    e = parity_errors(R, J, Ro, Jo, fo.abs_scales(m, U), fo.element_scales(m, U))
+    _report(f"{name}/f32", e)
+    # the residual stays FP64
+    assert e["term"][0] <= TOL64 and e["elem"][0] <= TOL64_ELEM and e["plain"][0] <= TOL64
+    assert e["term"][1] <= TOL32 and e["elem"][1] <= TOL32 and e["plain"][1] <= TOL32_PLAIN
 
 
 def test_sia_parity(case):
@@ -172,54 +190,53 @@ def test_outputs_fully_overwritten(case):
     assert torch.equal(Rn, R0) and torch.equal(Jn, J0)
 
 
-def test_icesheet_full_size_sampled_rows():
-    """Ice-sheet configuration (~2.5M wedges) in the benchmark's launch configuration:
-    sampled Jacobian rows and residual entries against the oracle on the cells around
-    them, plus symmetry J_ij = J_ji on sampled entries."""
+def test_icesheet_full_mesh_parity():
+    """Ice-sheet configuration (2,487,040 wedges, 2,750,000 dofs, 108M nonzeros) in the
+    benchmark's launch configuration: every residual entry and every Jacobian value, FP64
+    and FP32, against the oracle.  The oracle rows of each range of vertex columns come from
+    the cells around them, in host processes started by "spawn" (they never touch the
+    device) that read the GPU arrays from files."""
+    import multiprocessing as mp
+    import os
+    import shutil
+    import time
+
+    import oracle_pool
     m, U = config1_icesheet()
     print(f"\n[case] icesheet: cells={m.n_cells} dofs={m.n_dofs}", flush=True)
     M = gpu_mesh(m)
     Ud = to_dev(U)
     R, Jv = M.jacobian(Ud)
+    R32, J32 = M.jacobian(Ud, dtype="f32")
     rowptr, colidx = M.pattern()
     torch.cuda.synchronize()
-    R = R.cpu().numpy()
-    Jv = Jv.cpu().numpy()
-    rowptr = rowptr.cpu().numpy()
-    colidx = colidx.cpu().numpy()
-    rng = np.random.default_rng(123)
-    L = m.n_layers
-    sel = np.unique(np.concatenate([
-        rng.choice(m.n_dofs, 48, replace=False),
-        [0, 1, m.n_dofs - 1, m.n_dofs - 2],
-        2 * (rng.choice(m.n_verts, 6) * (L + 1)),          # bed rows
-        2 * (rng.choice(m.n_verts, 6) * (L + 1) + L) + 1,  # surface rows
-    ]))
-    r_o, J_o, cells = fo.assemble_rows(m, U, sel)
-    rs, js = fo.abs_scales(m, U, cells=cells)
-    for n, i in enumerate(sel):
-        cols = colidx[rowptr[i]:rowptr[i + 1]]
-        vals = Jv[rowptr[i]:rowptr[i + 1]]
-        ref = J_o[n].toarray().ravel()
-        assert np.array_equal(np.sort(J_o[n].indices), cols)
-        assert np.max(np.abs(vals - ref[cols])) <= TOL64 * js[i], i
-        assert abs(R[i] - r_o[n]) <= TOL64 * rs[i], i
-    # symmetry on sampled entries (the Jacobian is the Hessian of an energy)
-    for i in rng.choice(m.n_dofs, 200, replace=False):
-        cols = colidx[rowptr[i]:rowptr[i + 1]]
-        for jj in cols[:: max(1, len(cols) // 6)]:
-            p = rowptr[i] + np.searchsorted(cols, jj)
-            cj = colidx[rowptr[jj]:rowptr[jj + 1]]
-            q = rowptr[jj] + np.searchsorted(cj, i)
-            assert colidx[q] == i
-            assert abs(Jv[p] - Jv[q]) <= 1e-12 * max(abs(Jv[p]), abs(Jv[rowptr[i]:rowptr[i + 1]]).max())
-    # the FP32 Jacobian in the same launch configuration, on the same sampled rows
-    R32, J32 = M.jacobian(Ud, dtype="f32")
-    torch.cuda.synchronize()
-    R32 = R32.cpu().numpy()
-    J32 = J32.cpu().numpy().astype(np.float64)
-    for n, i in enumerate(sel):
-        cols = colidx[rowptr[i]:rowptr[i + 1]]
-        ref = J_o[n].toarray().ravel()
-        assert np.max(np.abs(J32[rowptr[i]:rowptr[i + 1]] - ref[cols])) <= TOL32 * js[i], i
-        assert abs(R32[i] - r_o[n]) <= TOL64 * rs[i], i
+    d = oracle_pool.scratch_dir()
+    try:
+        files = {}
+        for k, t in (("R", R), ("J", Jv), ("J32", J32), ("rowptr", rowptr), ("colidx", colidx)):
+            files[k] = os.path.join(d, k + ".npy")
+            np.save(files[k], t.cpu().numpy())
+        # the FP32 pass writes the same FP64 residual
+        assert torch.equal(R, R32)
+        del Jv, J32
+        t0 = time.perf_counter()
+        workers = min(16, len(os.sched_getaffinity(0)))
+        with mp.get_context("spawn").Pool(workers, initializer=oracle_pool.init_worker,
+                                          initargs=(config1_icesheet, files)) as pool:
+            res = pool.map(oracle_pool.compare_columns, oracle_pool.column_ranges(m.n_verts, 8 * workers),
+                           chunksize=1)
+        tot = oracle_pool.merge(res)
+        print(f"[icesheet] oracle comparison of {tot['rows']} rows on {workers} processes in "
+              f"{time.perf_counter() - t0:.1f} s", flush=True)
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    for key in ("R", "J", "J32"):
+        t = tot[key]
+        print(f"[icesheet/{key}] term {t['term']:.2e} (row {t['term_row']}), elem {t['elem']:.2e} "
+              f"(row {t['elem_row']}), plain {t['plain']:.2e}", flush=True)
+    assert tot["pattern_ok"] and tot["rows"] == m.n_dofs
+    for key in ("R", "J"):
+        t = tot[key]
+        assert t["term"] <= TOL64 and t["elem"] <= TOL64_ELEM and t["plain"] <= TOL64, (key, t)
+    t = tot["J32"]
+    assert t["term"] <= TOL32 and t["elem"] <= TOL32 and t["plain"] <= TOL32_PLAIN, t

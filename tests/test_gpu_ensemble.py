@@ -7,7 +7,7 @@ import torch
 from fo_inputs import ensemble_member
 from oracle import fo_oracle as fo
 
-from gpu_util import gpu_jacobian, gpu_mesh, row_scaled_errors, to_dev
+from gpu_util import gpu_jacobian, gpu_mesh, parity_errors, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -65,9 +65,9 @@ def test_ensemble_member_vs_oracle(members, k):
     Jg = sp.csr_matrix((Js[k].cpu().numpy(), colidx.cpu().numpy().astype(np.int64), rowptr.cpu().numpy()),
                        shape=(M.n_dofs, M.n_dofs))
     Ro, Jo = fo.assemble(m, U)
-    rs, js = fo.abs_scales(m, U)
-    er, ej = row_scaled_errors(Rs[k].cpu().numpy(), Jg, Ro, Jo, rs, js)
-    assert er <= 1e-12 and ej <= 1e-12
+    e = parity_errors(Rs[k].cpu().numpy(), Jg, Ro, Jo, fo.abs_scales(m, U), fo.element_scales(m, U))
+    print(f"[ensemble member {k}] {e}")
+    assert max(e["term"]) <= 1e-12 and max(e["elem"]) <= 1e-12 and max(e["plain"]) <= 1e-12
     assert m.A != members[0][0].A or k == 0     # members carry their own rate factor
 
 
@@ -92,9 +92,9 @@ def test_hexahedral_ensemble_equals_single_mesh():
     (m, U), M = hex_members[-1], Ms[-1]
     R1, J1 = gpu_jacobian(M, U)
     Ro, Jo = fo.assemble(m, U)
-    rs, js = fo.abs_scales(m, U)
-    er, ej = row_scaled_errors(R1, J1, Ro, Jo, rs, js)
-    assert er <= 1e-12 and ej <= 1e-12
+    e = parity_errors(R1, J1, Ro, Jo, fo.abs_scales(m, U), fo.element_scales(m, U))
+    print(f"[hex ensemble, largest member] {e}")
+    assert max(e["term"]) <= 1e-12 and max(e["elem"]) <= 1e-12 and max(e["plain"]) <= 1e-12
 
 
 def test_wedge_ensemble_with_general_exponent():
@@ -116,9 +116,11 @@ def test_wedge_ensemble_with_general_exponent():
     for (m, U), R in zip(mus, Rs):
         Ro = fo.residual(m, U)
         rs, _ = fo.abs_scales(m, U)
-        assert np.max(np.abs(R.cpu().numpy() - Ro) / rs) <= 1e-12
+        er_, _ = fo.element_scales(m, U)
+        d = np.abs(R.cpu().numpy() - Ro)
+        assert np.max(d / rs) <= 1e-12 and np.max(d / er_) <= 1e-12 and d.max() <= 1e-12 * np.abs(Ro).max()
     import scipy.sparse as sp
-    for dtype, tdt, tol in (("f64", torch.float64, 1e-12), ("f32", torch.float32, 1e-5)):
+    for dtype, tdt, tol, tol_plain in (("f64", torch.float64, 1e-12, 1e-12), ("f32", torch.float32, 1e-5, 1e-6)):
         Js = [torch.full((M.nnz,), float("nan"), dtype=tdt, device="cuda") for M in Ms]
         E.assemble(Us, Rs, Js, dtype=dtype)
         torch.cuda.synchronize()
@@ -130,6 +132,6 @@ def test_wedge_ensemble_with_general_exponent():
             Jg = sp.csr_matrix((J.double().cpu().numpy(), colidx.cpu().numpy().astype(np.int64),
                                 rowptr.cpu().numpy()), shape=(M.n_dofs, M.n_dofs))
             Ro, Jo = fo.assemble(m, U)
-            rs, js = fo.abs_scales(m, U)
-            er, ej = row_scaled_errors(R.cpu().numpy(), Jg, Ro, Jo, rs, js)
-            assert er <= 1e-12 and ej <= tol, (dtype, er, ej)
+            e = parity_errors(R.cpu().numpy(), Jg, Ro, Jo, fo.abs_scales(m, U), fo.element_scales(m, U))
+            assert e["term"][0] <= 1e-12 and e["elem"][0] <= 1e-12 and e["plain"][0] <= 1e-12, (dtype, e)
+            assert e["term"][1] <= tol and e["elem"][1] <= tol and e["plain"][1] <= tol_plain, (dtype, e)

@@ -43,7 +43,9 @@ def test_newton_matches_oracle_solution(cap, jdt):
     # the residual the GPU reached, recomputed by the oracle
     f0 = np.linalg.norm(fo.residual(m, np.zeros_like(Ug)))
     assert np.linalg.norm(fo.residual(m, Ug)) <= 1.01e-8 * f0
-    assert np.abs(Ug - U_ref).max() <= 1e-5 * np.abs(U_ref).max()
+    diff = np.abs(Ug - U_ref).max() / np.abs(U_ref).max()
+    print(f"[newton {jdt}] max |U - U_oracle| / max |U_oracle| = {diff:.2e}")
+    assert diff <= 1e-6
 
 
 @pytest.mark.parametrize("jdt", ["f64", "f32"])
@@ -58,7 +60,9 @@ def test_newton_pcg_matches_oracle_solution(cap, jdt):
     Ug = U.cpu().numpy()
     f0 = np.linalg.norm(fo.residual(m, np.zeros_like(Ug)))
     assert np.linalg.norm(fo.residual(m, Ug)) <= 1.01e-8 * f0
-    assert np.abs(Ug - U_ref).max() <= 1e-5 * np.abs(U_ref).max()
+    diff = np.abs(Ug - U_ref).max() / np.abs(U_ref).max()
+    print(f"[newton pcg {jdt}] max |U - U_oracle| / max |U_oracle| = {diff:.2e}")
+    assert diff <= 1e-6
 
 
 def test_newton_sia_init_and_slab():
@@ -124,4 +128,6 @@ def test_newton_wedge_general_exponent(cap, n_glen, A, tol_ref):
     Ug = U.cpu().numpy()
     f0 = np.linalg.norm(fo.residual(m1, np.zeros_like(Ug)))
     assert np.linalg.norm(fo.residual(m1, Ug)) <= 1.01e-8 * f0
-    assert np.abs(Ug - U_ref).max() <= 1e-5 * np.abs(U_ref).max()
+    diff = np.abs(Ug - U_ref).max() / np.abs(U_ref).max()
+    print(f"[newton n={n_glen}] max |U - U_oracle| / max |U_oracle| = {diff:.2e}")
+    assert diff <= 1e-6
