@@ -8,9 +8,12 @@ the FP64 CSR Jacobian values; no zero fill is needed) with all inputs resident i
 Prints one JSON line with cells/s, the roofline position of the assembly kernel
 (algorithmic bytes over its HIP-event-timed duration, and algorithmic flops against the
 FP64 vector peak), the measured HBM traffic when the committed counter figures match the
-kernel source, and the FP64 CPU oracle timed on a bounded sample.
+kernel source, and the FP64 CPU oracle timed on a bounded sample.  Beside the headline,
+the same object carries the rest of the metric: the FP32-Jacobian assembly on the same mesh
+(jacobian_f32), one Newton solve on it (newton), and Newton wall time from the learned
+initial guess against the shallow-ice guess on held-out ice caps (learned_vs_plain).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu] [--jdtype f64|f32]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 20] [--no-cpu] [--no-extra] [--jdtype f64|f32]
     python bench.py --workload ensemble     # 64-member batch in one persistent launch
     python bench.py --workload newton       # Newton solves, FP64 and FP32 Jacobian values
 """
@@ -34,6 +37,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, vendor figure (256 CUs x 12
 FLOPS_PER_WEDGE = 4600.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assemble_icesheet_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2204_04321_amd", "csrc", "fo_assemble.hip")
+KERNEL_NAME = "owner_kernel<wedge, Jacobian, JT, n=3>"
 
 
 def algorithmic_bytes(m, nnz: int, jac_bytes: int = 8) -> int:
@@ -237,6 +241,94 @@ def newton_bench(args):
     M.close()
 
 
+def time_assembly(M, m, Ud, jdtype, steps, warmup):
+    """Warm up, then time `steps` consecutive R+J assemblies between HIP events on the current
+    stream, with the assembly kernel itself timed by HIP events on the library's stream.  Also
+    the median per-step time and 100 consecutive evaluations (the paper's fill timing repeats
+    the evaluation 100 times)."""
+    import torch
+    R = torch.empty(M.n_dofs, dtype=torch.float64, device="cuda")
+    J = torch.empty(M.nnz, dtype=torch.float64 if jdtype == "f64" else torch.float32, device="cuda")
+    for _ in range(warmup):
+        M.jacobian(Ud, dtype=jdtype, R=R, Jvals=J)
+    torch.cuda.synchronize()
+    M.profile(True)
+    M.profile_read()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        M.jacobian(Ud, dtype=jdtype, R=R, Jvals=J)
+    ev1.record()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    kern_ms, launches = M.profile_read()
+    M.profile(False)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record()
+    for i in range(steps):
+        M.jacobian(Ud, dtype=jdtype, R=R, Jvals=J)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    median_ms = per_step[len(per_step) // 2] if len(per_step) % 2 else 0.5 * (
+        per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2])
+    ev0.record()
+    for _ in range(100):
+        M.jacobian(Ud, dtype=jdtype, R=R, Jvals=J)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_100 = ev0.elapsed_time(ev1)
+    kern_s = kern_ms / launches / 1e3
+    jb = 8 if jdtype == "f64" else 4
+    alg = algorithmic_bytes(m, M.nnz, jb)
+    return {"total_ms": total_ms, "ms_step": total_ms / steps, "kernel_s": kern_s, "median_ms": median_ms,
+            "ms_100": ms_100, "alg_bytes": alg, "achieved_gbs": alg / kern_s / 1e9}
+
+
+def newton_line(M):
+    """One Newton solve on the ice-sheet mesh from the shallow-ice guess to tol 1e-8 (FP64
+    Jacobian values, GMRES with the column preconditioner), after an untimed first call."""
+    import torch
+    U = torch.zeros(M.n_dofs, dtype=torch.float64, device="cuda")
+    opts = M.newton_opts(jac_dtype="f64")
+    ws = torch.empty(M.workspace_bytes(opts), dtype=torch.uint8, device="cuda")
+    M.newton_solve(U, workspace=ws, init="sia", max_newton=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = M.newton_solve(U, workspace=ws, init="sia")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    del ws
+    return {"wall_s": wall, "status": rep["status"], "newton_its": rep["newton_its"], "gmres_its": rep["lin_its"],
+            "residual_calls": rep["residual_calls"], "jacobian_calls": rep["jacobian_calls"],
+            "final_rel": rep["final_rel"], "ms_total_fill": rep["ms_total_fill"],
+            "ms_prec_construction": rep["ms_prec_construction"], "ms_linear_solve": rep["ms_linear_solve"],
+            "ms_total_solve": rep["ms_total_solve"],
+            "config": "ice-sheet wedge mesh, shallow-ice start, tol 1e-8 of ||F(0)||, GMRES(100) with the "
+                      "vertical-column block-LU preconditioner, lin_rtol 1e-6, FP64 Jacobian values"}
+
+
+WEIGHTS = os.path.join(ROOT, "paper_2204_04321_amd", "weights", "learned_guess.npz")
+
+
+def learned_line(n_caps, pool):
+    """Newton wall time from the learned guess against the shallow-ice guess on held-out ice
+    caps (seeds 20000...), with the committed network; paired speedup exp(mean log ratio) and
+    its 99% t-interval, as the paper treats timing ratios (Sec. 4.5)."""
+    if not os.path.exists(WEIGHTS):
+        return None
+    from paper_2204_04321_amd.learned import evaluate, load_model
+    model = load_model(WEIGHTS)
+    rep = evaluate(model, range(20000, 20000 + n_caps), fallback=1, pool=pool)
+    out = {k: v for k, v in rep.items() if k != "rows"}
+    out["config"] = (f"{n_caps} held-out seeded ice caps (2000 points, ~38k wedges each, seeds 20000-"
+                     f"{20000 + n_caps - 1}), tol 1e-8; learned side includes features, inference, "
+                     "smoothing and the residual fallback check")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,7 +336,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--jdtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline assembly line (no FP32, Newton and learned-guess keys)")
     ap.add_argument("--cpu-cells", type=int, default=200_000)
+    ap.add_argument("--learned-caps", type=int, default=40)
     ap.add_argument("--workload", choices=["icesheet", "ensemble", "newton"], default="icesheet",
                     help="icesheet: the headline single-mesh line; ensemble: the 64-member batch; "
                          "newton: Newton solves on the ice-sheet mesh with FP64 and FP32 Jacobians")
@@ -264,14 +359,14 @@ def main():
         newton_bench(args)
         return
 
-    # the oracle's all-cores pool is forked before the first device call
+    # host process pools are forked before the first device call
+    import multiprocessing as mp
     pool, workers = None, 0
     if not args.no_cpu:
-        import multiprocessing as mp
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
         pool = mp.get_context("fork").Pool(workers)
+    mesh_pool = None if args.no_extra else mp.get_context("fork").Pool(4)
 
-    import numpy as np
     import torch
 
     from fo_inputs import config1_icesheet
@@ -286,61 +381,23 @@ def main():
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t_setup) * 1e3
     Ud = torch.from_numpy(U).cuda()
-    R = torch.empty(M.n_dofs, dtype=torch.float64, device="cuda")
-    J = torch.empty(M.nnz, dtype=torch.float64 if args.jdtype == "f64" else torch.float32, device="cuda")
     print(f"[bench] cells {M.n_cells} dofs {M.n_dofs} nnz {M.nnz}; warmup {args.warmup}",
           file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        M.jacobian(Ud, dtype=args.jdtype, R=R, Jvals=J)
-    torch.cuda.synchronize()
-    M.profile(True)
-    M.profile_read()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        M.jacobian(Ud, dtype=args.jdtype, R=R, Jvals=J)
-    ev1.record()
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    kern_ms, launches = M.profile_read()
-    M.profile(False)
-    ms_step = total_ms / args.steps
-    kern_avg_s = kern_ms / launches / 1e3
-    jb = 8 if args.jdtype == "f64" else 4
-    alg = algorithmic_bytes(m, M.nnz, jb)
-    achieved = alg / kern_avg_s / 1e9
+    a = time_assembly(M, m, Ud, args.jdtype, args.steps, args.warmup)
     traffic = measured_traffic() if args.jdtype == "f64" else None
     pk = measured_peaks()
-    # after the timed steps: the median of per-step times and 100 consecutive R+J
-    # evaluations (the paper's fill timing repeats the evaluation 100 times)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    evs[0].record()
-    for i in range(args.steps):
-        M.jacobian(Ud, dtype=args.jdtype, R=R, Jvals=J)
-        evs[i + 1].record()
-    torch.cuda.synchronize()
-    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
-    median_ms = per_step[len(per_step) // 2] if len(per_step) % 2 else 0.5 * (
-        per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2])
-    ev0.record()
-    for _ in range(100):
-        M.jacobian(Ud, dtype=args.jdtype, R=R, Jvals=J)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_100 = ev0.elapsed_time(ev1)
-    print(f"[bench] {ms_step:.3f} ms/step, assembly kernel {kern_avg_s * 1e3:.3f} ms, "
-          f"{achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    print(f"[bench] {a['ms_step']:.3f} ms/step, assembly kernel {a['kernel_s'] * 1e3:.3f} ms, "
+          f"{a['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    kern_avg_s, achieved = a["kernel_s"], a["achieved_gbs"]
 
     out = {
         "metric": "cells/s FO-Stokes residual+Jacobian assembly (%HBM roof)",
-        "value": M.n_cells * args.steps / (total_ms / 1e3),
+        "value": M.n_cells * args.steps / (a["total_ms"] / 1e3),
         "unit": "cells/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": a["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -352,7 +409,7 @@ def main():
             "cells": M.n_cells, "base_triangles": int(m.n_base_cells), "dofs": M.n_dofs,
             "nnz": M.nnz, "jacobian_values": args.jdtype,
         },
-        "timing": {"median_step_ms": median_ms, "consecutive_100_ms": ms_100, "mesh_setup_ms": setup_ms},
+        "timing": {"median_step_ms": a["median_ms"], "consecutive_100_ms": a["ms_100"], "mesh_setup_ms": setup_ms},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -360,9 +417,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "owner_kernel<wedge, Jacobian, JT, n=3>",
+            "kernel": KERNEL_NAME,
             "kernel_ms": kern_avg_s * 1e3,
-            "algorithmic_bytes": alg,
+            "algorithmic_bytes": a["alg_bytes"],
             # the same figure against the streaming copy rate measured on this device type
             "peak_measured": pk["copy_gbs"] if pk else None,
             "frac_of_measured": achieved / pk["copy_gbs"] if pk else None,
@@ -376,6 +433,30 @@ def main():
                                          if pk else None)},
         },
     }
+    if not args.no_extra:
+        other = "f32" if args.jdtype == "f64" else "f64"
+        b = time_assembly(M, m, Ud, other, args.steps, args.warmup)
+        print(f"[bench] {other} J: {b['ms_step']:.3f} ms/step, kernel {b['kernel_s'] * 1e3:.3f} ms",
+              file=sys.stderr, flush=True)
+        out["jacobian_" + other] = {
+            "value": M.n_cells * args.steps / (b["total_ms"] / 1e3), "unit": "cells/s", "ms_per_step": b["ms_step"],
+            "median_step_ms": b["median_ms"], "consecutive_100_ms": b["ms_100"],
+            "roofline": {"bound": "hbm", "achieved": b["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": b["achieved_gbs"] / HBM_PEAK_GBS, "kernel_ms": b["kernel_s"] * 1e3,
+                         "algorithmic_bytes": b["alg_bytes"]},
+            "config": f"same mesh and inputs, Jacobian values in {other.upper()} (residual, strain rate and "
+                      "viscosity FP64)"}
+        print("[bench] Newton solve", file=sys.stderr, flush=True)
+        out["newton"] = newton_line(M)
+        print(f"[bench] Newton {out['newton']['wall_s']:.3f} s, {out['newton']['newton_its']} its",
+              file=sys.stderr, flush=True)
+    M.close()
+    del Ud
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        print("[bench] learned vs plain Newton on held-out caps", file=sys.stderr, flush=True)
+        out["learned_vs_plain"] = learned_line(args.learned_caps, mesh_pool)
+        mesh_pool.close()
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(m, U, args.cpu_cells)
@@ -384,7 +465,6 @@ def main():
         pool.close()
         pool.join()
     print(json.dumps(out))
-    M.close()
 
 
 if __name__ == "__main__":

@@ -116,7 +116,7 @@ fo_status fo_assemble_jacobian(const fo_mesh *mesh, const double *U_dev, double 
 fo_status fo_initial_guess_sia(const fo_mesh *mesh, double *U_dev, void *stream);
 
 /* ---- Newton solve (eq. linearsystem: J(U_k) delta = -F(U_k), U_{k+1} = U_k + alpha_k delta) ---- */
-typedef enum { FO_INIT_USER = 0, FO_INIT_SIA = 1 } fo_init;
+typedef enum { FO_INIT_USER = 0, FO_INIT_SIA = 1, FO_INIT_LEARNED = 2 } fo_init;
 /* Linear solver of each Newton step.  FO_LIN_GMRES is the method (GMRES, Sec. 3.1).
  * FO_LIN_PCG, an option beyond the paper, runs preconditioned conjugate gradients: the
  * Newton Jacobian is the Hessian of a convex energy and the column block preconditioner is
@@ -133,8 +133,13 @@ typedef struct {
   int32_t max_lin;         /* GMRES iterations per Newton step (500) */
   int32_t jac_dtype;       /* FO_F64 or FO_F32 Jacobian values for GMRES and preconditioner */
   int32_t max_backtracks;  /* line-search halvings of alpha (10) */
-  int32_t init;            /* FO_INIT_USER: U_dev holds the guess; FO_INIT_SIA: shallow-ice guess */
+  int32_t init;            /* FO_INIT_USER: U_dev holds the guess; FO_INIT_SIA: shallow-ice guess;
+                              FO_INIT_LEARNED: fo_initial_guess_learned with the fields below */
   int32_t linear_solver;   /* fo_linear_solver (FO_LIN_GMRES); lin_rtol and max_lin apply to both */
+  const float *mlp_params; /* FO_INIT_LEARNED: device [fo_mlp_param_count()] network parameters */
+  const float *mlp_norm;   /* FO_INIT_LEARNED: device [20] feature means then standard deviations */
+  int32_t learned_fallback;/* FO_INIT_LEARNED: fallback rule of fo_initial_guess_learned (1) */
+  int32_t learned_smooth;  /* FO_INIT_LEARNED: smoothing sweeps of fo_initial_guess_learned (0) */
 } fo_newton_opts;
 
 typedef struct {
@@ -152,12 +157,17 @@ typedef struct {
   double ms_linear_solve;
   double ms_total_solve;
   double res_hist[64];     /* ||F||/||F(0)|| before each Newton step (first 64) */
+  int32_t init_used;       /* fo_init whose guess the solve started from (FO_INIT_LEARNED falls
+                              back to FO_INIT_SIA when the network's guess is rejected) */
+  int32_t learned_fallbacks; /* 1 if FO_INIT_LEARNED was asked for and its guess was rejected */
 } fo_newton_report;
 
 void fo_newton_default_opts(fo_newton_opts *opts);
 
 /* Device workspace needed by fo_newton_solve for these options (0 on bad options):
- * Jacobian values, GMRES basis (restart+1 vectors), column factors, vectors. */
+ * Jacobian values, GMRES basis (restart+1 vectors; with FO_INIT_LEARNED at least the
+ * learned guess's workspace, which shares that region before the first Krylov step),
+ * column factors, vectors. */
 size_t fo_newton_workspace_bytes(const fo_mesh *mesh, const fo_newton_opts *opts);
 
 /* Damped Newton with GMRES(restart) right-preconditioned by block LU of each vertical
@@ -220,14 +230,30 @@ fo_status fo_mse_grad(const float *Y_dev, const float *T_dev, int64_t n, float *
 fo_status fo_adam_step(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int32_t n,
                        float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
 
-/* Initial velocity U = U_sia + 10 sinh(Y) (Y: the network's column outputs, L must be 10),
- * replaced by the shallow-ice guess U_sia if any value is non-finite, or, with fallback = 1,
- * if ||F(U)|| > ||F(U_sia)|| (fallback = 0: non-finite values only).  *used_network (host)
- * tells which one was kept.  Workspace: fo_learned_workspace_bytes, 256-byte aligned.
- * Synchronises. */
+/* Training targets T [V][22] (FP32) from a converged solution U_dev and the shallow-ice guess
+ * U_sia_dev of the same mesh (both FP64 [n_dofs], L must be 10): the correction of the
+ * shallow-ice profile in the network's output scale, T = asinh((U - U_sia) / 10 m/yr), in
+ * dof order (a column's 22 dofs are contiguous). */
+fo_status fo_learned_targets(const fo_mesh *mesh, const double *U_dev, const double *U_sia_dev, float *T_dev,
+                             void *stream);
+
+/* Feature normalisation norm_dev [20] (FP32) from raw features X_dev [n_rows][10]: the 10
+ * column means, then the 10 standard deviations (n - 1 in the denominator, n_rows >= 2)
+ * plus 1e-6.  Sums in FP64, one pass per moment, deterministic.  If Xn_dev is not NULL it
+ * receives the normalised features (X - mean) / std [n_rows][10], as fo_column_features
+ * computes them from the same norm. */
+fo_status fo_feature_stats(const float *X_dev, int64_t n_rows, float *norm_dev, float *Xn_dev, void *stream);
+
+/* Initial velocity U = U_sia + D, D the network's correction 10 sinh(Y) (Y: its column
+ * outputs, L must be 10) after `smooth_sweeps` >= 0 Jacobi sweeps over the base mesh,
+ * D_v <- (D_v + mean of D over v's base-mesh neighbours) / 2 (per dof of the column; the
+ * network predicts each column alone).  Replaced by the shallow-ice guess U_sia if any
+ * value is non-finite, or, with fallback = 1, if ||F(U)|| > ||F(U_sia)|| (fallback = 0:
+ * non-finite values only).  *used_network (host) tells which one was kept.  Workspace:
+ * fo_learned_workspace_bytes, 256-byte aligned.  Synchronises. */
 size_t fo_learned_workspace_bytes(const fo_mesh *mesh);
 fo_status fo_initial_guess_learned(const fo_mesh *mesh, const float *params_dev, const float *norm_dev,
-                                   double *U_dev, int32_t fallback, void *workspace_dev,
+                                   double *U_dev, int32_t fallback, int32_t smooth_sweeps, void *workspace_dev,
                                    size_t workspace_bytes, int32_t *used_network, void *stream);
 
 /* Measurement support: while enabled, every assembly call records HIP events on

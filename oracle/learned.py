@@ -19,6 +19,11 @@ reference and the GPU kernels:
 * outputs: asinh((u - u_sia) / 10 m/yr) for (u, v) at the L+1 levels, in dof order: the
   network corrects the shallow-ice profile (which carries the rate factor A and the
   surface slope), so U = U_sia + 10 sinh(y);
+* feature normalisation: column means and standard deviations (n - 1 denominator)
+  plus 1e-6 over the training features;
+* the guess: U = U_sia + D with D = 10 sinh(y), after k Jacobi sweeps over the base
+  mesh D_v <- (D_v + mean of D_w over the base neighbours w of v) / 2, each dof of a
+  column separately;
 * loss: mean squared error over the batch and the 22 outputs;
 * optimiser: Adam with bias correction.
 """
@@ -88,6 +93,33 @@ def column_targets(mesh, U, U_sia):
 
 def targets_to_velocity(Y, U_sia):
     return U_sia + OUT_SCALE * np.sinh(Y).reshape(-1)
+
+
+def feature_norm(X):
+    """Means, then standard deviations (n - 1 denominator) + 1e-6, of features X [n, 10]."""
+    X = np.asarray(X, dtype=np.float64)
+    return np.concatenate([X.mean(axis=0), X.std(axis=0, ddof=1) + 1e-6])
+
+
+def smooth_columns(mesh, D, sweeps):
+    """k Jacobi sweeps of D [V, m] over the base mesh, written as loops over the neighbour
+    lists: each sweep replaces D_v by the average of D_v and the mean of its neighbours."""
+    ptr, nb = base_neighbours(mesh)
+    D = np.array(D, dtype=np.float64, copy=True)
+    for _ in range(sweeps):
+        new = D.copy()
+        for v in range(mesh.n_verts):
+            w = nb[ptr[v]:ptr[v + 1]]
+            if w.shape[0]:
+                new[v] = 0.5 * (D[v] + D[w].mean(axis=0))
+        D = new
+    return D
+
+
+def learned_velocity(mesh, Y, U_sia, sweeps=0):
+    """The learned guess before its fallback check: U_sia + smoothed 10 sinh(Y)."""
+    D = OUT_SCALE * np.sinh(np.asarray(Y, dtype=np.float64)).reshape(mesh.n_verts, -1)
+    return U_sia + smooth_columns(mesh, D, sweeps).reshape(-1)
 
 
 def init_params(rng, layers=LAYERS):

@@ -39,6 +39,8 @@ class NewtonOpts(C.Structure):
         ("tol", C.c_double), ("max_newton", C.c_int32), ("lin_rtol", C.c_double),
         ("gmres_restart", C.c_int32), ("max_lin", C.c_int32), ("jac_dtype", C.c_int32),
         ("max_backtracks", C.c_int32), ("init", C.c_int32), ("linear_solver", C.c_int32),
+        ("mlp_params", C.c_void_p), ("mlp_norm", C.c_void_p), ("learned_fallback", C.c_int32),
+        ("learned_smooth", C.c_int32),
     ]
 
 
@@ -50,6 +52,7 @@ class NewtonReport(C.Structure):
         ("ms_total_fill", C.c_double), ("ms_prec_construction", C.c_double),
         ("ms_linear_solve", C.c_double), ("ms_total_solve", C.c_double),
         ("res_hist", C.c_double * 64),
+        ("init_used", C.c_int32), ("learned_fallbacks", C.c_int32),
     ]
 
     def as_dict(self):
@@ -58,7 +61,7 @@ class NewtonReport(C.Structure):
         return d
 
 
-FO_INIT_USER, FO_INIT_SIA = 0, 1
+FO_INIT_USER, FO_INIT_SIA, FO_INIT_LEARNED = 0, 1, 2
 FO_LIN_GMRES, FO_LIN_PCG = 0, 1
 
 _lib = None
@@ -90,7 +93,9 @@ def _declare(lib):
         "fo_mse_grad": (C.c_int, [vp, vp, C.c_int64, vp, vp, vp]),
         "fo_adam_step": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]),
         "fo_learned_workspace_bytes": (C.c_size_t, [vp]),
-        "fo_initial_guess_learned": (C.c_int, [vp, vp, vp, vp, i32, vp, C.c_size_t, C.POINTER(C.c_int32), vp]),
+        "fo_initial_guess_learned": (C.c_int, [vp, vp, vp, vp, i32, i32, vp, C.c_size_t, C.POINTER(C.c_int32), vp]),
+        "fo_learned_targets": (C.c_int, [vp, vp, vp, vp, vp]),
+        "fo_feature_stats": (C.c_int, [vp, C.c_int64, vp, vp, vp]),
         "fo_status_string": (C.c_char_p, [C.c_int]),
         "fo_last_error": (C.c_char_p, []),
     }

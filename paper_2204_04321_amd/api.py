@@ -127,7 +127,9 @@ class Mesh:
             if k == "jac_dtype":
                 v = FO_F64 if v in ("f64", FO_F64) else FO_F32
             elif k == "init":
-                v = {"user": _lib.FO_INIT_USER, "sia": _lib.FO_INIT_SIA}.get(v, v)
+                v = {"user": _lib.FO_INIT_USER, "sia": _lib.FO_INIT_SIA, "learned": _lib.FO_INIT_LEARNED}.get(v, v)
+            elif k in ("mlp_params", "mlp_norm"):
+                v = _ptr(v) if isinstance(v, torch.Tensor) else v
             elif k == "linear_solver":
                 v = {"gmres": _lib.FO_LIN_GMRES, "pcg": _lib.FO_LIN_PCG}.get(v, v)
             setattr(o, k, v)
@@ -166,18 +168,27 @@ class Mesh:
         return F
 
     def learned_guess(self, params: torch.Tensor, norm: torch.Tensor, out: torch.Tensor | None = None,
-                      workspace: torch.Tensor | None = None, fallback: int = 1, stream=None):
-        """(U, used_network): network guess with the shallow-ice fallback (1: non-finite or
-        larger residual norm; 0: non-finite only)."""
+                      workspace: torch.Tensor | None = None, fallback: int = 1, smooth: int = 0, stream=None):
+        """(U, used_network): network guess, its correction smoothed by `smooth` sweeps over the
+        base mesh, with the shallow-ice fallback (1: non-finite or larger residual norm; 0:
+        non-finite only)."""
         U = out if out is not None else torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
         need = int(_lib.lib().fo_learned_workspace_bytes(self.handle))
         if workspace is None or workspace.numel() < need:
             workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
         used = C.c_int32()
         check(_lib.lib().fo_initial_guess_learned(self.handle, _ptr(params), _ptr(norm), _ptr(U), int(fallback),
-                                                  _ptr(workspace), workspace.numel(), C.byref(used),
+                                                  int(smooth), _ptr(workspace), workspace.numel(), C.byref(used),
                                                   _stream(stream)))
         return U, bool(used.value)
+
+    def learned_targets(self, U: torch.Tensor, U_sia: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        """Training targets [V, 22] (FP32) of a converged solution U against the shallow-ice guess."""
+        self._check_vec(U)
+        self._check_vec(U_sia)
+        T = out if out is not None else torch.empty(self.n_verts, 22, dtype=torch.float32, device=self.device)
+        check(_lib.lib().fo_learned_targets(self.handle, _ptr(U), _ptr(U_sia), _ptr(T), _stream(stream)))
+        return T
 
     # ---- measurement ----------------------------------------------------------------------
     def profile(self, on: bool = True):
@@ -257,6 +268,17 @@ class MLP:
         check(_lib.lib().fo_mlp_backward(_ptr(self.params), _ptr(X), B, _ptr(acts), _ptr(dY), _ptr(dacts),
                                          _ptr(self.grads), _stream(stream)))
         return self.grads
+
+    @staticmethod
+    def feature_stats(X: torch.Tensor, normalised: bool = False, stream=None):
+        """Normalisation [20] (10 means, 10 standard deviations + 1e-6) of raw features X [n, 10];
+        with normalised=True also the normalised features: (norm, Xn)."""
+        if X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] != 10:
+            raise ValueError("expected FP32 features [n, 10]")
+        norm = torch.empty(20, dtype=torch.float32, device=X.device)
+        Xn = torch.empty_like(X) if normalised else None
+        check(_lib.lib().fo_feature_stats(_ptr(X), X.shape[0], _ptr(norm), _ptr(Xn), _stream(stream)))
+        return (norm, Xn) if normalised else norm
 
     @staticmethod
     def mse_grad(Y, T, loss: torch.Tensor | None = None, stream=None):

@@ -130,6 +130,11 @@ fo_status launch_assemble(const fo_mesh *m, const double *U, double *R, void *J,
                           int kind, bool want_jac, hipStream_t s);
 fo_status launch_sia(const fo_mesh *m, double *U, hipStream_t s);
 fo_status launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// learned initial guess (fo_learned.hip), shared with fo_newton_solve's FO_INIT_LEARNED
+size_t learned_workspace_bytes(const fo_mesh *m);
+fo_status learned_guess(const fo_mesh *m, const float *params, const float *norm, double *U, int32_t fallback,
+                        int32_t sweeps, void *ws, size_t ws_bytes, int32_t *used_network,
+                        int32_t *n_residuals, hipStream_t s);
 // kernel timing brackets (no-ops unless profiling is enabled on the mesh)
 fo_status profile_begin(const fo_mesh *m, hipStream_t s);
 fo_status profile_end(const fo_mesh *m, hipStream_t s);

@@ -173,14 +173,87 @@ __global__ void adam_kernel(int n, float *__restrict__ p, const float *__restric
   p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
-// U = U_sia + 10 sinh(Y) (a column's outputs are its dofs in order); flag non-finite values
-__global__ void output_kernel(int64_t n, const float *__restrict__ Y, const double *__restrict__ Us,
-                              double *__restrict__ U, int *__restrict__ bad) {
+// D = 10 sinh(Y): the network's correction of the shallow-ice profile (a column's outputs are
+// its dofs in order)
+__global__ void correction_kernel(int64_t n, const float *__restrict__ Y, double *__restrict__ D) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double u = Us[i] + 10.0 * sinh(double(Y[i]));
+  D[i] = 10.0 * sinh(double(Y[i]));
+}
+
+// One Jacobi sweep over the base mesh: Dn_v = (D_v + mean of D_w over v's neighbours w != v) / 2,
+// for each of the nd dofs of a column.
+__global__ void smooth_kernel(int V, int nd, const int32_t *__restrict__ nbr_ptr, const int32_t *__restrict__ nbr_idx,
+                              const double *__restrict__ D, double *__restrict__ Dn) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(V) * nd) return;
+  const int v = int(i / nd), r = int(i % nd);
+  double s = 0.0;
+  int cnt = 0;
+  for (int p = nbr_ptr[v]; p < nbr_ptr[v + 1]; ++p) {
+    const int w = nbr_idx[p];
+    if (w == v) continue;
+    s += D[int64_t(w) * nd + r];
+    ++cnt;
+  }
+  const double d = D[i];
+  Dn[i] = cnt > 0 ? 0.5 * (d + s / double(cnt)) : d;
+}
+
+// U = U_sia + D; flag non-finite values
+__global__ void compose_kernel(int64_t n, const double *__restrict__ D, const double *__restrict__ Us,
+                               double *__restrict__ U, int *__restrict__ bad) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double u = Us[i] + D[i];
   U[i] = u;
   if (!isfinite(u)) atomicOr(bad, 1);
+}
+
+// T = asinh((U - U_sia) / 10), rounded to FP32
+__global__ void targets_kernel(int64_t n, const double *__restrict__ U, const double *__restrict__ Us,
+                               float *__restrict__ T) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T[i] = float(asinh((U[i] - Us[i]) / 10.0));
+}
+
+// Xn = (X - mean) / std per feature, in FP64 and rounded once, as features_kernel normalises
+__global__ void normalise_kernel(int64_t n, const float *__restrict__ X, const float *__restrict__ norm,
+                                 float *__restrict__ Xn) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = int(i % NIN);
+  Xn[i] = float((double(X[i]) - double(norm[j])) / double(norm[NIN + j]));
+}
+
+// Per feature column j (one block each): mean, then sqrt(sum (x - mean)^2 / (n - 1)) + 1e-6.
+__global__ __launch_bounds__(256) void feature_stats_kernel(const float *__restrict__ X, int64_t n,
+                                                            float *__restrict__ norm) {
+  const int j = blockIdx.x;
+  __shared__ double red[4];
+  __shared__ double mean_s;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) s += double(X[r * NIN + j]);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) mean_s = (red[0] + red[1] + red[2] + red[3]) / double(n);
+  __syncthreads();
+  const double mean = mean_s;
+  double q = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    const double d = double(X[r * NIN + j]) - mean;
+    q += d * d;
+  }
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    norm[j] = float(mean);
+    norm[NIN + j] = float(sqrt((red[0] + red[1] + red[2] + red[3]) / double(n - 1)) + 1e-6);
+  }
 }
 
 fo_status gemm(int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
@@ -286,7 +359,7 @@ extern "C" fo_status fo_adam_step(float *P, const float *G, float *Mom, float *V
 namespace {
 constexpr size_t ALIGN = 256;
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
-struct LLayout { size_t F, acts, Y, Us, R, partial, dots, flag, total; };
+struct LLayout { size_t F, acts, Y, Us, R, D, partial, dots, flag, total; };
 LLayout llayout(const fo_mesh *m) {
   const size_t V = size_t(m->view.V), n = size_t(m->view.n_dofs);
   LLayout L{};
@@ -297,6 +370,7 @@ LLayout llayout(const fo_mesh *m) {
   L.Y = take(4 * V * NOUT);
   L.Us = take(8 * n);
   L.R = take(8 * n);
+  L.D = take(8 * 2 * n);
   L.partial = take(8 * size_t(multidot_blocks(int64_t(n))));
   L.dots = take(16);
   L.flag = take(16);
@@ -305,33 +379,45 @@ LLayout llayout(const fo_mesh *m) {
 }
 }  // namespace
 
-extern "C" size_t fo_learned_workspace_bytes(const fo_mesh *m) { return m ? llayout(m).total : 0; }
+namespace fo {
+size_t learned_workspace_bytes(const fo_mesh *m) { return llayout(m).total; }
 
-extern "C" fo_status fo_initial_guess_learned(const fo_mesh *m, const float *P, const float *norm, double *U,
-                                              int32_t fallback, void *ws, size_t ws_bytes, int32_t *used_network,
-                                              void *stream) {
+fo_status learned_guess(const fo_mesh *m, const float *P, const float *norm, double *U, int32_t fallback,
+                        int32_t sweeps, void *ws, size_t ws_bytes, int32_t *used_network, int32_t *n_residuals,
+                        hipStream_t s) {
+  if (n_residuals) *n_residuals = 0;
   if (!m || !P || !norm || !U || !ws) return fail(FO_EINVAL, "fo_initial_guess_learned: NULL argument");
   if (fallback != 0 && fallback != 1) return fail(FO_EINVAL, "fo_initial_guess_learned: fallback must be 0 or 1");
+  if (sweeps < 0 || sweeps > 10000) return fail(FO_EINVAL, "fo_initial_guess_learned: smooth_sweeps must be in 0..10000");
   if (m->view.L + 1 != NOUT / 2) return fail(FO_EINVAL, "fo_initial_guess_learned: the network predicts 11 levels (L = 10)");
   if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(FO_EINVAL, "fo_initial_guess_learned: workspace must be 256-byte aligned");
   const LLayout L = llayout(m);
   if (ws_bytes < L.total) return fail(FO_EINVAL, "fo_initial_guess_learned: workspace too small");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   char *w = static_cast<char *>(ws);
   float *F = reinterpret_cast<float *>(w + L.F), *acts = reinterpret_cast<float *>(w + L.acts);
   float *Y = reinterpret_cast<float *>(w + L.Y);
   double *Us = reinterpret_cast<double *>(w + L.Us), *R = reinterpret_cast<double *>(w + L.R);
+  double *D0 = reinterpret_cast<double *>(w + L.D);
   double *part = reinterpret_cast<double *>(w + L.partial), *dots = reinterpret_cast<double *>(w + L.dots);
   int *flag = reinterpret_cast<int *>(w + L.flag);
   const int V = m->view.V;
   const int64_t n = m->view.n_dofs;
+  double *D1 = D0 + n;
   fo_status st;
   if ((st = launch_sia(m, Us, s)) != FO_OK) return st;
-  if ((st = fo_column_features(m, norm, F, stream)) != FO_OK) return st;
+  if ((st = fo_column_features(m, norm, F, s)) != FO_OK) return st;
   if ((st = mlp_forward_impl(P, F, V, acts, Y, s)) != FO_OK) return st;
   if ((st = launch_fill_zero(flag, 16, s)) != FO_OK) return st;
-  hipLaunchKernelGGL(output_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, Y, Us, U, flag);
-  FO_LAUNCH_CHECK("output_kernel");
+  const unsigned nb = unsigned((n + 255) / 256);
+  hipLaunchKernelGGL(correction_kernel, dim3(nb), dim3(256), 0, s, n, Y, D0);
+  FO_LAUNCH_CHECK("correction_kernel");
+  for (int k = 0; k < sweeps; ++k) {
+    hipLaunchKernelGGL(smooth_kernel, dim3(nb), dim3(256), 0, s, V, NOUT, m->nbr_ptr, m->nbr_idx, D0, D1);
+    FO_LAUNCH_CHECK("smooth_kernel");
+    std::swap(D0, D1);
+  }
+  hipLaunchKernelGGL(compose_kernel, dim3(nb), dim3(256), 0, s, n, D0, Us, U, flag);
+  FO_LAUNCH_CHECK("compose_kernel");
   // fall back to the shallow-ice guess if the network output is non-finite, or (fallback = 1)
   // if its residual norm exceeds the shallow-ice guess's
   double hv[2] = {0.0, 0.0};
@@ -339,6 +425,7 @@ extern "C" fo_status fo_initial_guess_learned(const fo_mesh *m, const float *P, 
   FO_HIP_TRY(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   if (fallback == 1) {
     if ((st = launch_assemble(m, Us, R, nullptr, FO_F64, FO_JAC_NEWTON, false, s)) != FO_OK) return st;
+    if (n_residuals) ++*n_residuals;
     if ((st = multidot(n, nullptr, 0, 0, R, part, dots, s)) != FO_OK) return st;
     FO_HIP_TRY(hipMemcpyAsync(&hv[1], dots, sizeof(double), hipMemcpyDeviceToHost, s));
   }
@@ -346,6 +433,7 @@ extern "C" fo_status fo_initial_guess_learned(const fo_mesh *m, const float *P, 
   bool use_nn = bad == 0;
   if (use_nn && fallback == 1) {
     if ((st = launch_assemble(m, U, R, nullptr, FO_F64, FO_JAC_NEWTON, false, s)) != FO_OK) return st;
+    if (n_residuals) ++*n_residuals;
     if ((st = multidot(n, nullptr, 0, 0, R, part, dots, s)) != FO_OK) return st;
     FO_HIP_TRY(hipMemcpyAsync(&hv[0], dots, sizeof(double), hipMemcpyDeviceToHost, s));
     FO_HIP_TRY(hipStreamSynchronize(s));
@@ -354,5 +442,38 @@ extern "C" fo_status fo_initial_guess_learned(const fo_mesh *m, const float *P, 
   if (!use_nn) FO_HIP_TRY(hipMemcpyAsync(U, Us, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   FO_HIP_TRY(hipStreamSynchronize(s));
   if (used_network) *used_network = use_nn ? 1 : 0;
+  return FO_OK;
+}
+}  // namespace fo
+
+extern "C" size_t fo_learned_workspace_bytes(const fo_mesh *m) { return m ? llayout(m).total : 0; }
+
+extern "C" fo_status fo_initial_guess_learned(const fo_mesh *m, const float *P, const float *norm, double *U,
+                                              int32_t fallback, int32_t smooth_sweeps, void *ws, size_t ws_bytes,
+                                              int32_t *used_network, void *stream) {
+  return learned_guess(m, P, norm, U, fallback, smooth_sweeps, ws, ws_bytes, used_network, nullptr,
+                       static_cast<hipStream_t>(stream));
+}
+
+extern "C" fo_status fo_learned_targets(const fo_mesh *m, const double *U, const double *Us, float *T, void *stream) {
+  if (!m || !U || !Us || !T) return fail(FO_EINVAL, "fo_learned_targets: NULL argument");
+  if (m->view.L + 1 != NOUT / 2) return fail(FO_EINVAL, "fo_learned_targets: the network predicts 11 levels (L = 10)");
+  const int64_t n = m->view.n_dofs;
+  hipLaunchKernelGGL(targets_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     n, U, Us, T);
+  FO_LAUNCH_CHECK("targets_kernel");
+  return FO_OK;
+}
+
+extern "C" fo_status fo_feature_stats(const float *X, int64_t n_rows, float *norm, float *Xn, void *stream) {
+  if (!X || !norm || n_rows < 2) return fail(FO_EINVAL, "fo_feature_stats: NULL argument or fewer than 2 rows");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(feature_stats_kernel, dim3(NIN), dim3(256), 0, s, X, n_rows, norm);
+  FO_LAUNCH_CHECK("feature_stats_kernel");
+  if (Xn) {
+    const int64_t n = n_rows * NIN;
+    hipLaunchKernelGGL(normalise_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, X, norm, Xn);
+    FO_LAUNCH_CHECK("normalise_kernel");
+  }
   return FO_OK;
 }

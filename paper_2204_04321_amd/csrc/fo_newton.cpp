@@ -24,7 +24,7 @@ constexpr size_t ALIGN = 256;
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t J, R, Rt, Ut, dU, W, Z, T, fac, V, partial, dots, total;
+  size_t J, R, Rt, Ut, dU, W, Z, T, fac, V, V_bytes, partial, dots, total;
 };
 
 Layout layout(const fo_mesh *m, const fo_newton_opts *o) {
@@ -43,7 +43,9 @@ Layout layout(const fo_mesh *m, const fo_newton_opts *o) {
   L.Z = take(8 * n);
   L.T = take(8 * n);
   L.fac = take(4 * size_t(m->view.V) * size_t(m->view.L + 1) * 12);
-  L.V = take(8 * n * size_t(mres + 1));
+  // the Krylov basis region also holds the learned guess's workspace before the first step
+  L.V_bytes = std::max(8 * n * size_t(mres + 1), o->init == FO_INIT_LEARNED ? learned_workspace_bytes(m) : 0);
+  L.V = take(L.V_bytes);
   L.partial = take(8 * std::max(size_t(multidot_blocks(int64_t(n))) * size_t(mres + 2),
                                  2 * size_t(dot2_blocks(int64_t(n)))));
   L.dots = take(8 * std::max(size_t(mres + 2), size_t(8)));   // GMRES: h and norms; CG: 6 scalars
@@ -255,6 +257,10 @@ extern "C" void fo_newton_default_opts(fo_newton_opts *o) {
   o->max_backtracks = 10;
   o->init = FO_INIT_USER;
   o->linear_solver = FO_LIN_GMRES;
+  o->mlp_params = nullptr;
+  o->mlp_norm = nullptr;
+  o->learned_fallback = 1;
+  o->learned_smooth = 0;
 }
 
 extern "C" size_t fo_newton_workspace_bytes(const fo_mesh *m, const fo_newton_opts *o) {
@@ -267,7 +273,9 @@ extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newto
   if (!m || !U || !o || !rep || !ws) return fail(FO_EINVAL, "fo_newton_solve: NULL argument");
   if (o->gmres_restart < 1 || o->gmres_restart > 500 || o->max_lin < 1 || o->max_newton < 0 ||
       !(o->tol > 0) || !(o->lin_rtol > 0) || o->max_backtracks < 0 ||
-      (o->jac_dtype != FO_F64 && o->jac_dtype != FO_F32) || (o->init != FO_INIT_USER && o->init != FO_INIT_SIA) ||
+      (o->jac_dtype != FO_F64 && o->jac_dtype != FO_F32) ||
+      (o->init != FO_INIT_USER && o->init != FO_INIT_SIA && o->init != FO_INIT_LEARNED) ||
+      (o->init == FO_INIT_LEARNED && (!o->mlp_params || !o->mlp_norm)) ||
       (o->linear_solver != FO_LIN_GMRES && o->linear_solver != FO_LIN_PCG))
     return fail(FO_EINVAL, "fo_newton_solve: bad options");
   if ((reinterpret_cast<uintptr_t>(U) & 15) || (reinterpret_cast<uintptr_t>(ws) & 255))
@@ -296,7 +304,19 @@ extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newto
     rep->residual_calls++;
     return s2;
   };
+  rep->init_used = o->init;
   if (o->init == FO_INIT_SIA && (st = launch_sia(m, U, c.s)) != FO_OK) return st;
+  if (o->init == FO_INIT_LEARNED) {
+    int32_t used = 0, n_res = 0;
+    if ((st = learned_guess(m, o->mlp_params, o->mlp_norm, U, o->learned_fallback, o->learned_smooth,
+                            c.ws + c.L.V, c.L.V_bytes, &used, &n_res, c.s)) != FO_OK)
+      return st;
+    rep->residual_calls += n_res;   // the residual-norm check of the fallback rule
+    if (!used) {
+      rep->init_used = FO_INIT_SIA;
+      rep->learned_fallbacks = 1;
+    }
+  }
   // ||F(0)||: the gravity load
   if ((st = launch_fill_zero(Ut, sizeof(double) * c.n, c.s)) != FO_OK) return st;
   if ((st = fill(Ut, Rt)) != FO_OK) return st;

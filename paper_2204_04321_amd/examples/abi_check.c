@@ -43,5 +43,7 @@ int main(void) {
   fo_newton_default_opts(&o);
   printf("default Newton tol %g, restart %d, linear solver %d, opts size %d\n", o.tol, (int)o.gmres_restart,
          (int)o.linear_solver, (int)sizeof o);
+  printf("learned init: fallback %d, smooth %d, report size %d\n", (int)o.learned_fallback, (int)o.learned_smooth,
+         (int)sizeof(fo_newton_report));
   return 0;
 }

@@ -30,6 +30,7 @@ def test_headers_declare_the_core_entry_points():
     names = declared_functions()
     for n in ("fo_mesh_create", "fo_mesh_destroy", "fo_mesh_info", "fo_jacobian_pattern",
               "fo_assemble_residual", "fo_assemble_jacobian", "fo_initial_guess_sia",
+              "fo_newton_solve", "fo_initial_guess_learned", "fo_learned_targets", "fo_feature_stats",
               "fo_status_string", "fo_last_error"):
         assert n in names
 
@@ -150,3 +151,5 @@ def test_plain_c_caller(tmp_path):
     _lib.lib().fo_newton_default_opts(ctypes.byref(o))
     assert o.linear_solver == _lib.FO_LIN_GMRES and o.gmres_restart == 100
     assert f"linear solver 0, opts size {ctypes.sizeof(_lib.NewtonOpts)}" in p.stdout
+    assert f"report size {ctypes.sizeof(_lib.NewtonReport)}" in p.stdout
+    assert o.learned_fallback == 1 and o.learned_smooth == 0 and not o.mlp_params

@@ -240,3 +240,39 @@ def test_icesheet_full_mesh_parity():
         assert t["term"] <= TOL64 and t["elem"] <= TOL64_ELEM and t["plain"] <= TOL64, (key, t)
     t = tot["J32"]
     assert t["term"] <= TOL32 and t["elem"] <= TOL32 and t["plain"] <= TOL32_PLAIN, t
+
+
+def _cell_of(m, U, t, k):
+    """Base cell t at layer k of an extruded mesh as a one-cell, one-layer mesh with the same
+    corner coordinates, elevations and velocities (bed friction only for k = 0)."""
+    vs = m.cells[t]
+    b = m.surface[vs] - m.thickness[vs]
+    z0 = b + m.sigma[k] * m.thickness[vs]
+    z1 = b + m.sigma[k + 1] * m.thickness[vs]
+    beta = m.beta[vs] if k == 0 else np.zeros(len(vs))
+    one = ExtrudedMesh(m.elem, m.xy[vs], np.arange(len(vs), dtype=np.int32)[None, :], z1, z1 - z0, beta,
+                       np.array([0.0, 1.0]), A=m.A, n=m.n)
+    L1 = m.n_layers + 1
+    Uc = U.reshape(-1, 2)[(vs[:, None] * L1 + np.array([k, k + 1])[None, :]).ravel()]
+    # reorder to the one-cell mesh's node numbering: vertex i, level 0 or 1 -> node 2 i + lev
+    return one, Uc.reshape(-1)
+
+
+def test_fp32_element_matrix_error_on_icesheet_cells():
+    """The FP32-Jacobian variant's error per element matrix, max |dJ_e| / max |J_e|, on 256
+    seeded cells of the ice-sheet configuration (each assembled alone, so the assembled
+    matrix is the element matrix), against the FP64 oracle."""
+    m, U = config1_icesheet()
+    rng = np.random.default_rng(77)
+    worst, errs = 0.0, []
+    for t, k in zip(rng.choice(m.n_base_cells, 256, replace=False), rng.integers(0, m.n_layers, 256)):
+        one, Uc = _cell_of(m, U, t, int(k))
+        M = gpu_mesh(one)
+        _, J32 = gpu_jacobian(M, Uc, "f32")
+        _, Jo = fo.assemble(one, Uc)
+        e = abs(J32 - Jo).max() / abs(Jo).max()
+        errs.append(e)
+        M.close()
+    errs = np.array(errs)
+    print(f"\n[icesheet cells, FP32 element matrices] max rel error {errs.max():.2e}, median {np.median(errs):.2e}")
+    assert errs.max() <= 1e-5

@@ -90,6 +90,71 @@ def test_adam_matches_reference():
     np.testing.assert_allclose(net.params.cpu().numpy(), pr, rtol=1e-5, atol=1e-6)
 
 
+def test_targets_and_feature_stats_match_reference():
+    from paper_2204_04321_amd.api import MLP
+    m = learned_mesh(20004, n_points=600)
+    M = gpu_mesh(m)
+    rng = np.random.default_rng(3)
+    Us = solve.sia_guess(m)
+    U = Us + rng.normal(size=m.n_dofs) * 40
+    T = M.learned_targets(to_dev(U), to_dev(Us)).cpu().numpy()
+    np.testing.assert_allclose(T, ol.column_targets(m, U, Us), rtol=2e-7, atol=1e-7)
+    X = rng.normal(size=(5000, 10)) * np.arange(1, 11) + np.arange(10) * 100.0
+    X = X.astype(np.float32)
+    norm, Xn = MLP.feature_stats(torch.from_numpy(X).cuda(), normalised=True)
+    ref = ol.feature_norm(X.astype(np.float64))
+    np.testing.assert_allclose(norm.cpu().numpy(), ref, rtol=1e-6)
+    np.testing.assert_allclose(Xn.cpu().numpy(), (X - ref[:10]) / ref[10:], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("sweeps", [0, 5])
+def test_smoothed_guess_matches_reference(sweeps):
+    """U = U_sia + smoothed 10 sinh(Y) (no fallback) against the reference composition, with
+    the reference's own features, normalisation and BF16-rounded network."""
+    m = learned_mesh(20005, n_points=500)
+    M = gpu_mesh(m)
+    rng = np.random.default_rng(sweeps + 11)
+    params = ol.init_params(rng)
+    for W, b in params:
+        b[:] = rng.normal(size=b.shape) * 0.1
+    flat = _flat(params)
+    params = _unflat(flat.astype(np.float64))
+    Fo = ol.column_features(m)
+    nrm = ol.feature_norm(Fo)
+    U, used = M.learned_guess(torch.from_numpy(flat).cuda(), torch.tensor(nrm, dtype=torch.float32).cuda(),
+                              fallback=0, smooth=sweeps)
+    assert used
+    Y, _ = ol.mlp_forward(params, ((Fo - nrm[:10]) / nrm[10:]).astype(np.float32).astype(np.float64))
+    Us = solve.sia_guess(m)
+    Uref = ol.learned_velocity(m, Y, Us, sweeps)
+    d = U.cpu().numpy() - Uref
+    print(f"\n[learned guess, {sweeps} sweeps] |dU| / |D| = {np.linalg.norm(d) / np.linalg.norm(Uref - Us):.2e}")
+    assert np.linalg.norm(d) <= 3e-3 * np.linalg.norm(Uref - Us)
+
+
+def test_newton_learned_init_reports_the_guess():
+    """FO_INIT_LEARNED inside fo_newton_solve starts from the same guess as
+    fo_initial_guess_learned and reports which guess it used."""
+    m = learned_mesh(20006, n_points=500)
+    M = gpu_mesh(m)
+    rng = np.random.default_rng(4)
+    flat = torch.from_numpy(_flat(ol.init_params(rng))).cuda()
+    nrm = torch.tensor(ol.feature_norm(ol.column_features(m)), dtype=torch.float32).cuda()
+    for fb in (0, 1):
+        U0, used = M.learned_guess(flat, nrm, fallback=fb, smooth=3)
+        U = torch.zeros(M.n_dofs, dtype=torch.float64, device="cuda")
+        rep = M.newton_solve(U, init="learned", mlp_params=flat, mlp_norm=nrm, learned_fallback=fb,
+                             learned_smooth=3, max_newton=0)
+        assert rep["status"] == -6           # the iteration cap of 0: U holds the starting guess
+        assert torch.equal(U, U0)
+        assert rep["learned_fallbacks"] == (0 if used else 1)
+        assert rep["init_used"] == (2 if used else 1)
+        rep = M.newton_solve(U, init="learned", mlp_params=flat, mlp_norm=nrm, learned_fallback=fb, learned_smooth=3)
+        assert rep["status"] == 0, rep
+    with pytest.raises(Exception):
+        M.newton_solve(U, init="learned", check_status=True)      # no network given
+
+
 def test_learned_guess_training_and_fallback():
     """Train on solutions the method generates (small meshes), then start Newton on held-out
     meshes from the learned guess and from the shallow-ice guess.  Asserted: training lowers
@@ -112,8 +177,8 @@ def test_learned_guess_training_and_fallback():
     for seed in range(31000, 31003):
         M = Mesh(learned_mesh(seed, n_points=500))
         Us = M.sia()
-        U0, used0 = M.learned_guess(model["params"], model["norm"], fallback=0)
-        U1, used1 = M.learned_guess(model["params"], model["norm"], fallback=1)
+        U0, used0 = M.learned_guess(model["params"], model["norm"], fallback=0, smooth=2)
+        U1, used1 = M.learned_guess(model["params"], model["norm"], fallback=1, smooth=2)
         assert used0 == 1 and bool(torch.isfinite(U0).all())
         n_nn = torch.linalg.vector_norm(M.residual(U0)).item()
         n_sia = torch.linalg.vector_norm(M.residual(Us)).item()

@@ -115,3 +115,44 @@ def test_target_transform_roundtrip():
     Us = rng.normal(size=m.n_dofs) * 300
     np.testing.assert_allclose(ol.targets_to_velocity(ol.column_targets(m, U, Us), Us), U, rtol=1e-12)
     np.testing.assert_array_equal(ol.column_targets(m, Us, Us), 0.0)
+
+
+def test_smoothing_pins():
+    """Jacobi smoothing of the correction: a field constant over the mesh is unchanged, one
+    sweep of a single spike gives the spike half its value and each neighbour the spike over
+    twice its neighbour count, and many sweeps drive any field towards a constant."""
+    from fo_inputs import learned_mesh
+    m = learned_mesh(20002, n_points=120)
+    ptr, nb = ol.base_neighbours(m)
+    const = np.full((m.n_verts, 3), 4.5)
+    np.testing.assert_allclose(ol.smooth_columns(m, const, 7), const, rtol=1e-15)
+    D = np.zeros((m.n_verts, 1))
+    D[10] = 8.0
+    S = ol.smooth_columns(m, D, 1)
+    assert S[10, 0] == 4.0
+    for w in nb[ptr[10]:ptr[11]]:
+        deg_w = ptr[w + 1] - ptr[w]
+        assert abs(S[w, 0] - 0.5 * 8.0 / deg_w) <= 1e-15
+    far = np.setdiff1d(np.arange(m.n_verts), np.concatenate([[10], nb[ptr[10]:ptr[11]]]))
+    assert np.all(S[far, 0] == 0.0)
+    R = np.random.default_rng(0).normal(size=(m.n_verts, 2))
+    S = ol.smooth_columns(m, R, 400)
+    assert S.std(axis=0).max() < 1e-2 * R.std(axis=0).min()
+
+
+def test_feature_norm_pins():
+    X = np.array([[1.0] * 10, [3.0] * 10, [5.0] * 10])
+    n = ol.feature_norm(X)
+    np.testing.assert_allclose(n[:10], 3.0)
+    np.testing.assert_allclose(n[10:], 2.0 + 1e-6)    # sqrt((4 + 0 + 4) / 2)
+
+
+def test_targets_roundtrip():
+    from fo_inputs import learned_mesh
+    m = learned_mesh(20003, n_points=80)
+    rng = np.random.default_rng(1)
+    Us = rng.normal(size=m.n_dofs) * 50
+    U = Us + rng.normal(size=m.n_dofs) * 30
+    Y = ol.column_targets(m, U, Us)
+    np.testing.assert_allclose(ol.targets_to_velocity(Y, Us), U, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(ol.learned_velocity(m, Y, Us, 0), U, rtol=1e-12, atol=1e-9)
