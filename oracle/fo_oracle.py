@@ -145,9 +145,18 @@ def node_column_field(mesh, f: np.ndarray) -> np.ndarray:
 # element-level evaluation
 # --------------------------------------------------------------------------------------
 
+def _local(X: np.ndarray) -> np.ndarray:
+    """Cell node coordinates relative to the cell's first node.  The derivatives of the
+    isoparametric map do not change under a translation of the cell (the basis derivatives
+    sum to zero), and the differences of coordinates of ~1e6 m are exact here, so this only
+    removes the rounding of the map's Jacobian entries formed from large absolute
+    coordinates (about 1e-16 x 1e6 m on a 5 m-thick margin cell)."""
+    return X - X[:, :1, :]
+
+
 def _geometry(ref: RefElement, X: np.ndarray):
     """X [nc, npe, 3] -> (gradN [nc,nq,npe,3], W [nc,nq]) by the isoparametric map."""
-    Jm = np.einsum("cai,qaj->cqij", X, ref.dN)          # dx_i / dxi_j
+    Jm = np.einsum("cai,qaj->cqij", _local(X), ref.dN)  # dx_i / dxi_j
     det = np.linalg.det(Jm)
     inv = np.linalg.inv(Jm)                              # dxi_j / dx_i  (index [j, i])
     gradN = np.einsum("qaj,cqji->cqai", ref.dN, inv)
@@ -247,7 +256,7 @@ def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | 
     bottom = (cell_ids % L) == 0
     if np.any(bottom):
         bidx = np.nonzero(bottom)[0]
-        Xb = X[bidx]
+        Xb = _local(X[bidx])
         tx = np.einsum("cai,ra->cri", Xb, ref.dNb[..., 0])
         ty = np.einsum("cai,ra->cri", Xb, ref.dNb[..., 1])
         dA = ref.bw[None, :] * np.linalg.norm(np.cross(tx, ty), axis=-1)   # [nb, nqb]
@@ -395,7 +404,7 @@ def energy(mesh, U, s_drive=None):
     E = np.sum(W * (dens + mesh.rho * mesh.g * (sx * uq + sy * vq)))
     L = mesh.n_layers
     bidx = np.arange(0, mesh.n_cells, L)
-    Xb = X[bidx]
+    Xb = _local(X[bidx])
     tx = np.einsum("cai,ra->cri", Xb, ref.dNb[..., 0])
     ty = np.einsum("cai,ra->cri", Xb, ref.dNb[..., 1])
     dA = ref.bw[None, :] * np.linalg.norm(np.cross(tx, ty), axis=-1)
