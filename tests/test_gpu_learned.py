@@ -104,7 +104,11 @@ def test_targets_and_feature_stats_match_reference():
     norm, Xn = MLP.feature_stats(torch.from_numpy(X).cuda(), normalised=True)
     ref = ol.feature_norm(X.astype(np.float64))
     np.testing.assert_allclose(norm.cpu().numpy(), ref, rtol=1e-6)
-    np.testing.assert_allclose(Xn.cpu().numpy(), (X - ref[:10]) / ref[10:], rtol=1e-5, atol=1e-6)
+    # (x - mean) / std in FP32 from FP32-rounded statistics: besides a few ulps of the
+    # result, the FP32 rounding of x and of the mean, relative to the column's spread
+    exact = (X.astype(np.float64) - ref[:10]) / ref[10:]
+    slack = 2.0 * (np.spacing(np.abs(X).max(0)).astype(np.float64) + np.spacing(np.abs(ref[:10]).astype(np.float32))) / ref[10:]
+    assert np.all(np.abs(Xn.cpu().numpy() - exact) <= 1e-6 * np.abs(exact) + slack)
 
 
 @pytest.mark.parametrize("sweeps", [0, 5])
