@@ -77,8 +77,9 @@ typedef struct fo_mesh fo_mesh;
  * solution-independent data, Sec. 4.1) and upload them.  FO_EDEGENERATE also
  * if a base vertex lies in no base cell.  On FO_EDEGENERATE nothing is
  * allocated.  FO_EINVAL also if a base vertex lies in more than 64
- * base cells or has more than 255 neighbours (one wave assembles a vertex
- * column's rows).  Synchronises `stream`. */
+ * base cells or has more than 100 neighbouring base vertices (one wave assembles
+ * a vertex column's rows in its share of the compute unit's LDS).  Synchronises
+ * `stream`. */
 fo_status fo_mesh_create(const fo_mesh_desc *desc, void *stream, fo_mesh **out);
 void fo_mesh_destroy(fo_mesh *mesh);
 
