@@ -257,6 +257,20 @@ fo_status fo_initial_guess_learned(const fo_mesh *mesh, const float *params_dev,
                                    double *U_dev, int32_t fallback, int32_t smooth_sweeps, void *workspace_dev,
                                    size_t workspace_bytes, int32_t *used_network, void *stream);
 
+/* fo_initial_guess_learned for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid hipMalloc): the same computation and
+ * result, with no workspace argument and no allocation.  Its workspace is a library-owned
+ * device array of FO_LEARNED_SCRATCH_BYTES on each GPU it runs on, held until the process
+ * ends; a mesh whose fo_learned_workspace_bytes exceeds it (about 14,000 base vertices) is
+ * rejected with FO_EINVAL before any device work.  The mesh's device must be current.  All
+ * calls on one GPU share that array and every call rewrites what it reads: calls that overlap
+ * on one GPU (other streams or threads) race, and the caller must serialise them.
+ * Synchronises. */
+#define FO_LEARNED_SCRATCH_BYTES ((size_t)32 << 20)
+fo_status fo_initial_guess_learned_noalloc(const fo_mesh *mesh, const float *params_dev, const float *norm_dev,
+                                           double *U_dev, int32_t fallback, int32_t smooth_sweeps,
+                                           int32_t *used_network, void *stream);
+
 /* Measurement support: while enabled, every assembly call records HIP events on
  * its stream around its main assembly kernel (not the zero fills).
  * fo_profile_read synchronises on the last event, returns the summed kernel

@@ -94,6 +94,7 @@ def _declare(lib):
         "fo_adam_step": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]),
         "fo_learned_workspace_bytes": (C.c_size_t, [vp]),
         "fo_initial_guess_learned": (C.c_int, [vp, vp, vp, vp, i32, i32, vp, C.c_size_t, C.POINTER(C.c_int32), vp]),
+        "fo_initial_guess_learned_noalloc": (C.c_int, [vp, vp, vp, vp, i32, i32, C.POINTER(C.c_int32), vp]),
         "fo_learned_targets": (C.c_int, [vp, vp, vp, vp, vp]),
         "fo_feature_stats": (C.c_int, [vp, C.c_int64, vp, vp, vp]),
         "fo_status_string": (C.c_char_p, [C.c_int]),

@@ -182,6 +182,17 @@ class Mesh:
                                                   _stream(stream)))
         return U, bool(used.value)
 
+    def learned_guess_noalloc(self, params: torch.Tensor, norm: torch.Tensor, out: torch.Tensor | None = None,
+                              fallback: int = 1, smooth: int = 0, stream=None):
+        """learned_guess with the library's own device array as workspace (no allocation in
+        the call; meshes up to the array's size)."""
+        U = out if out is not None else torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        used = C.c_int32()
+        check(_lib.lib().fo_initial_guess_learned_noalloc(self.handle, _ptr(params), _ptr(norm), _ptr(U),
+                                                          int(fallback), int(smooth), C.byref(used),
+                                                          _stream(stream)))
+        return U, bool(used.value)
+
     def learned_targets(self, U: torch.Tensor, U_sia: torch.Tensor, out: torch.Tensor | None = None, stream=None):
         """Training targets [V, 22] (FP32) of a converged solution U against the shallow-ice guess."""
         self._check_vec(U)

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "fo_device.h"
 #include "fo_internal.h"
@@ -452,6 +453,50 @@ extern "C" fo_status fo_initial_guess_learned(const fo_mesh *m, const float *P, 
                                               int32_t fallback, int32_t smooth_sweeps, void *ws, size_t ws_bytes,
                                               int32_t *used_network, void *stream) {
   return learned_guess(m, P, norm, U, fallback, smooth_sweeps, ws, ws_bytes, used_network, nullptr,
+                       static_cast<hipStream_t>(stream));
+}
+
+// Workspace of fo_initial_guess_learned_noalloc: a library-owned array on each device,
+// resolved to its device address once per device (the array's name in host code is a
+// host-side stand-in, never a device address) and held until the process ends.
+namespace {
+__device__ __align__(256) unsigned char scratch[FO_LEARNED_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+fo_status scratch_address(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) return fo::fail(FO_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fo::fail(FO_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return FO_OK;
+}
+}  // namespace
+
+extern "C" fo_status fo_initial_guess_learned_noalloc(const fo_mesh *m, const float *P, const float *norm, double *U,
+                                                      int32_t fallback, int32_t smooth_sweeps, int32_t *used_network,
+                                                      void *stream) {
+  if (!m) return fail(FO_EINVAL, "fo_initial_guess_learned_noalloc: NULL mesh");
+  const size_t need = llayout(m).total;
+  if (need > FO_LEARNED_SCRATCH_BYTES)
+    return fail(FO_EINVAL, "fo_initial_guess_learned_noalloc: mesh needs " + std::to_string(need) +
+                               " bytes of workspace, more than the library's " +
+                               std::to_string(size_t(FO_LEARNED_SCRATCH_BYTES)) + "-byte array");
+  int dev = -1;
+  FO_HIP_TRY(hipGetDevice(&dev));
+  if (dev != m->device)
+    return fail(FO_EINVAL, "fo_initial_guess_learned_noalloc: the mesh's device must be the current device");
+  void *ws = nullptr;
+  fo_status st = scratch_address(dev, &ws);
+  if (st != FO_OK) return st;
+  return learned_guess(m, P, norm, U, fallback, smooth_sweeps, ws, FO_LEARNED_SCRATCH_BYTES, used_network, nullptr,
                        static_cast<hipStream_t>(stream));
 }
 
