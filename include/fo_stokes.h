@@ -121,9 +121,12 @@ typedef enum { FO_INIT_USER = 0, FO_INIT_SIA = 1, FO_INIT_LEARNED = 2 } fo_init;
 /* Linear solver of each Newton step.  FO_LIN_GMRES is the method (GMRES, Sec. 3.1).
  * FO_LIN_PCG, an option beyond the paper, runs preconditioned conjugate gradients: the
  * Newton Jacobian is the Hessian of a convex energy and the column block preconditioner is
- * symmetric positive definite, so CG applies with a few vectors per iteration instead of
- * the growing Krylov basis; a step whose search direction shows non-positive curvature is
- * solved again by GMRES. */
+ * symmetric positive definite in exact arithmetic, so CG applies with a few vectors per
+ * iteration instead of the growing Krylov basis.  In floating point the operators are only
+ * nearly symmetric: the column factors are stored in FP32 (M^-1 symmetric to about 1e-7
+ * relative) and so are the Jacobian values with jac_dtype = FO_F32.  Should a search
+ * direction show non-positive curvature, the solve stops with FO_ENOTCONV (GMRES has no such
+ * requirement). */
 typedef enum { FO_LIN_GMRES = 0, FO_LIN_PCG = 1 } fo_linear_solver;
 
 typedef struct {
@@ -146,7 +149,7 @@ typedef struct {
 typedef struct {
   int32_t status;          /* fo_status of the solve */
   int32_t newton_its;
-  int64_t lin_its;         /* GMRES iterations summed over Newton steps */
+  int64_t lin_its;         /* linear-solver iterations (GMRES or CG) summed over Newton steps */
   int32_t residual_calls;  /* residual-only assemblies (line search, norms) */
   int32_t jacobian_calls;  /* residual + Jacobian assemblies */
   int32_t backtracks;

@@ -181,18 +181,18 @@ fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b
 }
 
 // Preconditioned conjugate gradients, x0 = 0, for the symmetric positive definite Newton
-// system (J is the Hessian of a convex energy; M, the column block preconditioner, is SPD).
-// Stops when ||b - J x|| <= lin_rtol ||b|| (the recursively updated residual) or after
-// max_lin iterations.  Sets `breakdown` (returning FO_OK) if a direction has non-positive
-// curvature, which an SPD system cannot produce; the caller then solves by GMRES.
+// system (J is the Hessian of a convex energy; M, the column block preconditioner, is SPD in
+// exact arithmetic).  Stops when ||b - J x|| <= lin_rtol ||b|| (the recursively updated
+// residual) or after max_lin iterations.  A direction with non-positive curvature (possible
+// only through rounding: FP32 Jacobian values and the FP32 column factors make J and M^-1
+// symmetric to about 1e-7 relative) ends the solve with FO_ENOTCONV.
 fo_status pcg(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b, double *x, int64_t &its,
-              double &rel_out, bool &breakdown) {
+              double &rel_out) {
   const int64_t n = c.n;
   double *r = c.dptr(c.L.W), *z = c.dptr(c.L.Z), *p = c.dptr(c.L.T), *q = c.dptr(c.L.V);
   const float *fac = reinterpret_cast<const float *>(c.ws + c.L.fac);
   fo_status st;
   its = 0;
-  breakdown = false;
   rel_out = 0.0;
   double bnorm;
   if ((st = norm2(c, b, bnorm)) != FO_OK) return st;
@@ -213,10 +213,9 @@ fo_status pcg(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b, 
   int slot = 0;
   while (its < o->max_lin) {
     if (!std::isfinite(rz)) return fail(FO_ENONFINITE, "pcg: non-finite Krylov vector");
-    if (!(rz > 0.0)) {
-      breakdown = true;
-      return FO_OK;
-    }
+    if (!(rz > 0.0))
+      return fail(FO_ENOTCONV, "pcg: the preconditioned residual has non-positive norm (M^-1 is not positive "
+                               "definite in this precision); use FO_LIN_GMRES");
     if ((st = spmv(c.m, Jv, o->jac_dtype, p, q, c.s)) != FO_OK) return st;              // q = J p
     if ((st = dot2(n, p, q, part, d, c.s)) != FO_OK) return st;                         // p . q
     if ((st = cg_step(n, d + 2 + 2 * slot, d, p, q, x, r, c.s)) != FO_OK) return st;    // x, r
@@ -227,10 +226,9 @@ fo_status pcg(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b, 
     FO_HIP_TRY(hipStreamSynchronize(c.s));
     const double pq = c.host[0], rz1 = c.host[2 + 2 * nxt], rr = c.host[3 + 2 * nxt];
     if (!std::isfinite(pq)) return fail(FO_ENONFINITE, "pcg: non-finite curvature");
-    if (!(pq > 0.0)) {   // this step's update of x used a meaningless length: GMRES redoes it
-      breakdown = true;
-      return FO_OK;
-    }
+    if (!(pq > 0.0))
+      return fail(FO_ENOTCONV, "pcg: a search direction has non-positive curvature (the Jacobian is not "
+                               "positive definite in this precision); use FO_LIN_GMRES");
     ++its;
     rel_out = std::sqrt(rr) / bnorm;
     if (rel_out <= o->lin_rtol) break;
@@ -349,12 +347,10 @@ extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newto
     if ((st = axpby(c.n, -1.0, R, 0.0, Rt, c.s)) != FO_OK) return st;
     int64_t lits = 0;
     double lrel = 0.0;
-    bool breakdown = o->linear_solver != FO_LIN_PCG;
-    if (!breakdown && (st = pcg(c, o, Jv, Rt, dU, lits, lrel, breakdown)) != FO_OK) return st;
-    if (breakdown) {   // GMRES: the default, or PCG met non-positive curvature
-      int64_t g_its = 0;
-      if ((st = gmres(c, o, Jv, Rt, dU, g_its, lrel)) != FO_OK) return st;
-      lits += g_its;
+    if (o->linear_solver == FO_LIN_PCG) {
+      if ((st = pcg(c, o, Jv, Rt, dU, lits, lrel)) != FO_OK) return st;
+    } else if ((st = gmres(c, o, Jv, Rt, dU, lits, lrel)) != FO_OK) {
+      return st;
     }
     rep->ms_linear_solve += ms_since(t0);
     rep->lin_its += lits;

@@ -191,3 +191,27 @@ def test_learned_guess_training_and_fallback():
         else:
             assert n_nn >= n_sia * (1 - 1e-12) and torch.equal(U1, Us)
         M.close()
+
+
+def test_committed_network_on_heldout_caps():
+    """The committed network (the bench's learned-vs-plain line) on fixed held-out caps: it
+    loads without pickling, every solve converges from either start, and the residual-checked
+    guess keeps the network only where its residual norm is the smaller one.  The measured
+    outcome on 200 held-out caps is that the learned start does not cut Newton time; the
+    paired speedup on this subset is printed, not asserted."""
+    import os
+    from paper_2204_04321_amd import _lib
+    from paper_2204_04321_amd.learned import evaluate, load_model
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2204_04321_amd", "weights", "learned_guess.npz")
+    model = load_model(path)
+    assert model["params"].numel() == int(_lib.lib().fo_mlp_param_count())
+    assert model["norm"].numel() == 20 and model["adam_step"] > 0
+    keys = ("newton_its_sia", "newton_its_learned", "speedup_geomean", "speedup_ci99", "fallbacks")
+    for fb in (1, 0):
+        rep = evaluate(model, range(20000, 20006), fallback=fb)
+        print(f"\n[committed network, fallback {fb}]", {k: rep[k] for k in keys})
+        assert rep["all_converged"]
+        assert 0 <= rep["fallbacks"] <= 6
+        if fb == 0:
+            assert rep["fallbacks"] == 0
