@@ -16,4 +16,7 @@ from .meshgen import (  # noqa: F401
     ellipse_mesh,
     smooth_velocity,
     perturbed,
+    boundary_edges,
+    floating_slab,
+    marine_sheet,
 )

@@ -42,6 +42,9 @@ class ExtrudedMesh:
     eps0: float = 1e-10       # strain-rate regularisation, yr^-1
     name: str = ""
     meta: dict = field(default_factory=dict)
+    front_edges: np.ndarray | None = None   # [n, 2] int32 base-vertex pairs of boundary edges under
+                                            # ocean back-pressure (sea level at z = 0), or None
+    rho_w: float = 1028.0                   # sea-water density, kg m^-3
 
     @property
     def n_layers(self) -> int:
@@ -211,6 +214,60 @@ def structured_box(nx: int, ny: int, n_layers: int, lx: float, ly: float, elem: 
     return xy, np.asarray(cells, dtype=np.int32), sigma
 
 
+def boundary_edges(cells: np.ndarray) -> np.ndarray:
+    """Edges [n, 2] of the base mesh that belong to exactly one cell, each in its cell's
+    counter-clockwise order (so the domain lies to the left of a -> b)."""
+    nv = cells.shape[1]
+    e = np.stack([cells, np.roll(cells, -1, axis=1)], axis=2).reshape(-1, 2).astype(np.int64)
+    key = np.minimum(e[:, 0], e[:, 1]) * (cells.max() + 1) + np.maximum(e[:, 0], e[:, 1])
+    _, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+    return e[cnt[inv] == 1].astype(np.int32)
+
+
+def floating_slab(elem: str = "hex", nx: int = 6, ny: int = 4, n_layers: int = 3, lx: float = 30e3,
+                  ly: float = 20e3, H: float = 400.0, rho: float = RHO_ICE, rho_w: float = 1028.0,
+                  jitter: float = 0.0, seed: int = 0):
+    """Freely floating slab of uniform thickness H on [0,lx]x[0,ly] (flat surface
+    s = (1 - rho/rho_w) H, base -(rho/rho_w) H below sea level, beta = 0), every lateral
+    side an ocean front.  jitter > 0 moves the interior vertices by up to jitter x spacing."""
+    xy, cells, sigma = structured_box(nx, ny, n_layers, lx, ly, elem=elem)
+    if jitter > 0:
+        rng = np.random.default_rng(seed)
+        h = min(lx / nx, ly / ny)
+        inner = (xy[:, 0] > 0) & (xy[:, 0] < lx) & (xy[:, 1] > 0) & (xy[:, 1] < ly)
+        xy = xy.copy()
+        xy[inner] += rng.uniform(-jitter * h, jitter * h, (int(inner.sum()), 2))
+    V = xy.shape[0]
+    Hv = np.full(V, H)
+    s = (1.0 - rho / rho_w) * Hv
+    return ExtrudedMesh(elem, xy, cells, s, Hv, np.zeros(V), sigma, rho=rho, name=f"floatslab_{elem}",
+                        front_edges=boundary_edges(cells), rho_w=rho_w)
+
+
+def marine_sheet(seed: int = 0, n_points: int = 1500, n_layers: int = 5, a: float = 80e3, b: float = 50e3,
+                 rho: float = RHO_ICE, rho_w: float = 1028.0):
+    """Marine ice sheet in an ellipse: bed rising inland from -700 m at the seaward end
+    (x = a) to +600 m at x = -a, a dome surface whose ice goes afloat where it is thinner
+    than flotation (there the base sits at -(rho/rho_w) H and beta = 0), log-normal beta
+    on grounded ice, and ocean fronts on the boundary edges whose two vertices have the base
+    below sea level.  Returns (mesh, U): U is the shallow-ice-shaped input plus 1% noise."""
+    rng = np.random.default_rng(seed)
+    xy, tri = ellipse_mesh(n_points, a, b, rng)
+    x, y = xy[:, 0] / a, xy[:, 1] / b
+    r2 = np.minimum(x * x + y * y, 1.0)
+    bed = 600.0 - 1300.0 * (x + 1.0) / 2.0 + 60.0 * _smooth_field(rng, xy, 10e3, 40e3)
+    H = np.maximum(60.0, 2200.0 * (1.0 - r2) ** 0.4 * (1.0 - 0.35 * (x + 1.0) / 2.0))
+    afloat = H < -(rho_w / rho) * bed
+    base = np.where(afloat, -(rho / rho_w) * H, bed)
+    s = base + H
+    beta = np.where(afloat, 0.0, np.exp(np.log(800.0) + 0.8 * _smooth_field(rng, xy, 10e3, 40e3)))
+    edges = boundary_edges(tri)
+    wet = (base[edges[:, 0]] < 0) & (base[edges[:, 1]] < 0)
+    m = ExtrudedMesh("wedge", xy, tri, s, H, beta, np.linspace(0.0, 1.0, n_layers + 1), rho=rho,
+                     A=1e-16, name="marine_sheet", front_edges=edges[wet], rho_w=rho_w)
+    return m, shallow_ice_velocity(m, rng)
+
+
 # --------------------------------------------------------------------------------------
 # velocity inputs
 # --------------------------------------------------------------------------------------
@@ -282,9 +339,13 @@ def shallow_ice_velocity(mesh: ExtrudedMesh, rng: np.random.Generator, noise_rel
     sg = mesh.sigma
     shape = H[:, None] ** (n + 1) - ((1.0 - sg[None, :]) * H[:, None]) ** (n + 1)       # [V, L+1]
     coef = -2.0 * A / (n + 1) * rg ** n * gn ** (n - 1)
-    ub = -rg * H[:, None] * g / np.maximum(mesh.beta, 1e-300)[:, None]
-    ubn = np.sqrt((ub * ub).sum(axis=1))
-    ub *= np.minimum(1.0, sliding_cap / np.maximum(ubn, 1e-300))[:, None]
+    with np.errstate(over="ignore", invalid="ignore"):
+        ub = -rg * H[:, None] * g / np.maximum(mesh.beta, 1e-300)[:, None]
+        ubn = np.sqrt((ub * ub).sum(axis=1))
+        ub *= np.minimum(1.0, sliding_cap / np.maximum(ubn, 1e-300))[:, None]
+    free = mesh.beta == 0          # no friction: sliding at the cap, down the surface slope
+    if np.any(free):
+        ub[free] = -sliding_cap * g[free] / np.maximum(gn[free], 1e-300)[:, None]
     U = ub[:, None, :] + (coef[:, None] * shape)[:, :, None] * g[:, None, :]
     U = U.reshape(-1)
     if noise_rel > 0:

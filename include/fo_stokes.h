@@ -68,6 +68,16 @@ typedef struct {
   double rho;                /* ice density > 0, kg m^-3 */
   double g;                  /* gravity > 0, m s^-2 */
   double eps0;               /* strain-rate regularisation >= 0, yr^-1 */
+  /* Ocean fronts (Sec. 2, lateral boundary condition on the marine margin), optional:
+   * n_front_edges base-mesh boundary edges (vertex pairs, either order) whose vertical
+   * faces take the ocean back-pressure, read as 2 mu eps_i . n - rho g (s - z) n_i =
+   * -rho_w g max(-z, 0) n_i with sea level at z = 0 (the printed max(z, 0) and its sign are
+   * garbled); the residual gains -int phi p n_i dA, p = rho g (s - z) - rho_w g max(-z, 0),
+   * a load that does not depend on U (the Jacobian is unchanged).  All other lateral faces
+   * stay natural.  Floating ice is described by beta = 0 where it floats. */
+  const int32_t *front_edges;/* host [n_front_edges][2], or NULL */
+  int32_t n_front_edges;     /* >= 0; 0 = no fronts */
+  double rho_w;              /* sea-water density > 0 (kg m^-3) when n_front_edges > 0 */
 } fo_mesh_desc;
 
 typedef struct fo_mesh fo_mesh;
@@ -78,8 +88,10 @@ typedef struct fo_mesh fo_mesh;
  * if a base vertex lies in no base cell.  On FO_EDEGENERATE nothing is
  * allocated.  FO_EINVAL also if a base vertex lies in more than 64
  * base cells or has more than 100 neighbouring base vertices (one wave assembles
- * a vertex column's rows in its share of the compute unit's LDS).  Synchronises
- * `stream`. */
+ * a vertex column's rows in its share of the compute unit's LDS), or if a front edge is
+ * not a boundary edge of the base mesh, appears twice, or a vertex lies on more than four
+ * front edges.  The front loads are integrated once here (memoised with the rest).
+ * Synchronises `stream`. */
 fo_status fo_mesh_create(const fo_mesh_desc *desc, void *stream, fo_mesh **out);
 void fo_mesh_destroy(fo_mesh *mesh);
 

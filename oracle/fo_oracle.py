@@ -18,8 +18,10 @@ What it computes (arXiv:2204.04321):
     + eps_xz^2 + eps_yz^2;
   * Sec. 2 boundary conditions: stress-free upper surface (natural), linear
     sliding 2 mu eps_i . n + beta u_i = 0 on the bed (reading: "= 0" is implied),
-    lateral margin natural (no term; reading, the ocean back-pressure term is
-    not part of this path);
+    lateral margin natural (no term) except on the marked ocean fronts, where the
+    lateral condition of Sec. 2 applies, read as 2 mu eps_i . n - rho g (s - z) n_i
+    = -rho_w g max(-z, 0) n_i with sea level z = 0 (the printed max(z, 0) and its sign
+    are garbled: water pushes on the submerged part, against the outward normal);
   * Sec. 3.1, eq. (residual): the discrete residual F(U) assembled from nodal
     basis functions phi_i and their gradients on prismatic (wedge) or
     hexahedral elements extruded from the 2D mesh;
@@ -273,6 +275,162 @@ def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | 
     return Re, Je, nodes
 
 
+# --------------------------------------------------------------------------------------
+# ocean back-pressure on the marine margin (Sec. 2, lateral boundary condition)
+# --------------------------------------------------------------------------------------
+
+def _gauss(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def front_faces(mesh):
+    """Lateral faces under ocean back-pressure: for each marked edge (a, b) of the base
+    mesh (oriented so that its cell is on the left, i.e. counter-clockwise in that cell) and
+    each layer k, the face with corners (a,k), (b,k), (b,k+1), (a,k+1).  Returns
+    (nodes [F, 4], outward unit normal [F, 2], edge length [F], z at the corners [F, 4],
+    surface s at a and b [F, 2])."""
+    E = np.asarray(mesh.front_edges, dtype=np.int64).reshape(-1, 2)
+    cells = mesh.cells.astype(np.int64)
+    ccw = set()
+    for c in cells:
+        for i in range(c.shape[0]):
+            ccw.add((int(c[i]), int(c[(i + 1) % c.shape[0]])))
+    E = E.copy()
+    for i, (a, b) in enumerate(E):
+        if (a, b) in ccw and (b, a) in ccw:
+            raise ValueError(f"front edge {a}-{b} is shared by two cells")
+        if (b, a) in ccw and (a, b) not in ccw:
+            E[i] = (b, a)
+        elif (a, b) not in ccw:
+            raise ValueError(f"front edge {a}-{b} is not an edge of the base mesh")
+    L = mesh.n_layers
+    L1 = L + 1
+    d = mesh.xy[E[:, 1]] - mesh.xy[E[:, 0]]
+    length = np.hypot(d[:, 0], d[:, 1])
+    normal = np.stack([d[:, 1], -d[:, 0]], axis=1) / length[:, None]   # domain on the left of a -> b
+    bed = mesh.surface - mesh.thickness
+    z = bed[:, None] + mesh.sigma[None, :] * mesh.thickness[:, None]   # [V, L+1]
+    k = np.arange(L)
+    a, b = E[:, 0][:, None], E[:, 1][:, None]
+    nodes = np.stack([a * L1 + k, b * L1 + k, b * L1 + k + 1, a * L1 + k + 1], axis=-1).reshape(-1, 4)
+    zc = np.stack([z[E[:, 0]][:, :-1], z[E[:, 1]][:, :-1], z[E[:, 1]][:, 1:], z[E[:, 0]][:, 1:]],
+                  axis=-1).reshape(-1, 4)
+    rep = lambda x: np.repeat(x, L, axis=0)
+    sab = np.stack([mesh.surface[E[:, 0]], mesh.surface[E[:, 1]]], axis=1)
+    return nodes, rep(normal), rep(length), zc, rep(sab)
+
+
+def _rational_integral(T, zl, dz, t0, t1):
+    """int_{t0}^{t1} T(t) zl(t)^3 / dz(t) dt for polynomials T (numpy.poly1d), zl, dz (dz linear
+    and positive on [t0, t1]).  With e the slope of dz and d its smaller end value: if
+    |e| <= d / 2 the pole -dz(0)/e lies at least two interval lengths away and 16-point Gauss
+    is exact to rounding; otherwise N = T zl^3 is divided by (t - t_p) (t_p the pole):
+    int N / dz = int S / e + N(t_p) / e * ln((t1 - t_p) / (t0 - t_p))."""
+    e = dz.c[0] if dz.order == 1 else 0.0
+    d = min(dz(t0), dz(t1))
+    N = T * zl ** 3
+    if abs(e) * (t1 - t0) <= 0.5 * d:
+        x, w = _gauss(16)
+        t = t0 + (t1 - t0) * x
+        return float(np.sum((t1 - t0) * w * N(t) / dz(t)))
+    tp = -dz.c[-1] / e
+    S, rem = np.polydiv(N.c, np.array([1.0, -tp]))
+    Si = np.polyint(np.poly1d(S))
+    return float((Si(t1) - Si(t0)) / e + rem[-1] / e * np.log((t1 - tp) / (t0 - tp)))
+
+
+def front_face_terms(mesh):
+    """Nodal loads of every front face, [F, 4 nodes, 2 components]: -int phi_node p n_c dA with
+    p = rho g (s - z) - rho_w g max(-z, 0).  The face lies in the vertical plane of its edge,
+    parametrised by t in [0,1] along the edge and zeta in [0,1] between its two levels
+    (z = zl(t) + zeta dz(t), zl and dz = zh - zl linear in t, dA = |edge| dz dt dzeta, phi
+    bilinear: (1-t)(1-zeta), t(1-zeta), t zeta, (1-t) zeta for the corners (a,k), (b,k),
+    (b,k+1), (a,k+1)).
+    * Ice term rho g (s - z): a polynomial of degree 3 in t and 2 in zeta, integrated exactly
+      by 2 x 2 Gauss.
+    * Water term rho_w g z (z < 0): split in t where the sea level crosses the lower or upper
+      edge of the face.  Where the whole layer is submerged the zeta integral is
+      int_0^1 z Z dz dzeta = dz (zl/2 + dz/6) (Z = 1 - zeta) or dz (zl/2 + dz/3) (Z = zeta),
+      a cubic in t after the T factor (2-point Gauss, exact).  Where it crosses,
+      u = zeta dz from 0 to -zl gives int z Z du = -zl^2/2 - zl^3/(6 dz) (Z = 1 - zeta) or
+      zl^3/(6 dz) (Z = zeta): the zl^2 part is a cubic in t (2-point Gauss), the zl^3/dz part
+      is integrated by _rational_integral.
+    Also returns per node |ice term| + |water term| (the scale of these entries' rounding)."""
+    nodes, normal, length, zc, sab = front_faces(mesh)
+    F = nodes.shape[0]
+    rg, rwg = mesh.rho * mesh.g, mesh.rho_w * mesh.g
+    x2, w2 = _gauss(2)
+    P = np.poly1d
+    Tf = [P([-1.0, 1.0]), P([1.0, 0.0])]           # 1 - t, t  (corner a, corner b)
+    corner = [(0, 0), (1, 0), (1, 1), (0, 1)]      # (T index, Z index) of the face corners
+    ice = np.zeros((F, 4))
+    wat = np.zeros((F, 4))
+    for f in range(F):
+        zl0, zl1, zh1, zh0 = zc[f]
+        zl = P([zl1 - zl0, zl0])
+        zh = P([zh1 - zh0, zh0])
+        dz = zh - zl
+        sf = P([sab[f, 1] - sab[f, 0], sab[f, 0]])
+        # ice term, exact 2 x 2 Gauss
+        for gt in range(2):
+            t = x2[gt]
+            for gz in range(2):
+                zeta = x2[gz]
+                zz = zl(t) + zeta * dz(t)
+                val = w2[gt] * w2[gz] * dz(t) * rg * (sf(t) - zz)
+                for c, (ti, zi) in enumerate(corner):
+                    ice[f, c] += val * (t if ti else 1 - t) * (zeta if zi else 1 - zeta)
+        # water term
+        br = [0.0, 1.0]
+        for q in (zl, zh):
+            if q.c[0] != 0:
+                r = -q.c[-1] / q.c[0]
+                if 0 < r < 1:
+                    br.append(r)
+        br = sorted(br)
+        for t0, t1 in zip(br[:-1], br[1:]):
+            if t1 <= t0:
+                continue
+            tm = 0.5 * (t0 + t1)
+            if zl(tm) >= 0:
+                continue                                   # dry
+            full = zh(tm) <= 0
+            for c, (ti, zi) in enumerate(corner):
+                T = Tf[ti]
+                if full:
+                    g = dz * (0.5 * zl + (dz / 3.0 if zi else dz / 6.0))
+                    val = sum((t1 - t0) * w2[k] * (T * g)((t0 + (t1 - t0) * x2[k])) for k in range(2))
+                else:
+                    sq = sum((t1 - t0) * w2[k] * (T * zl ** 2)((t0 + (t1 - t0) * x2[k])) for k in range(2))
+                    cu = _rational_integral(T, zl, dz, t0, t1) / 6.0
+                    val = cu if zi else -0.5 * sq - cu
+                wat[f, c] += rwg * val
+    ice *= length[:, None]
+    wat *= length[:, None]
+    tot = -(ice + wat)[:, :, None] * normal[:, None, :]
+    tot_abs = (np.abs(ice) + np.abs(wat))[:, :, None] * np.abs(normal)[:, None, :]
+    return nodes, tot, tot_abs
+
+
+def front_load(mesh, absolute: bool = False):
+    """Residual contribution [n_dofs] of the ocean fronts (zero without fronts); it does not
+    depend on U.  absolute=True: the per-term scale (sum of |quadrature terms|)."""
+    R = np.zeros(mesh.n_dofs)
+    fe = getattr(mesh, "front_edges", None)
+    if fe is None or len(fe) == 0:
+        return R
+    nodes, tot, tot_abs = front_face_terms(mesh)
+    vals = tot_abs if absolute else tot
+    dofs = 2 * nodes[:, :, None] + np.arange(2)[None, None, :]
+    return R + np.bincount(dofs.ravel(), weights=vals.ravel(), minlength=mesh.n_dofs)
+
+
+def _has_front(mesh):
+    fe = getattr(mesh, "front_edges", None)
+    return fe is not None and len(fe) > 0
+
+
 def _chunks(n, size):
     for s in range(0, n, size):
         yield np.arange(s, min(n, s + size))
@@ -303,6 +461,8 @@ def assemble(mesh, U: np.ndarray, want_jac: bool = True, picard: bool = False,
             cols = np.tile(dofs, (1, m)).ravel()
             Jc = sp.coo_matrix((Je.reshape(-1), (rows, cols)), shape=(nd, nd)).tocsr()
             J = Jc if J is None else J + Jc
+    if _has_front(mesh):      # per node, independent of U: exact on any row whose cells are all included
+        R += front_load(mesh)
     if want_jac and not cplx:
         J.sum_duplicates()
         J.sort_indices()
@@ -333,6 +493,10 @@ def _row_sums_and_matrix(mesh, U, picard, chunk, cells, absolute):
         cols = np.tile(dofs, (1, m)).ravel()
         Jc = sp.coo_matrix((np.abs(Je).reshape(-1), (rows, cols)), shape=(nd, nd)).tocsr()
         Jabs = Jc if Jabs is None else Jabs + Jc
+    if _has_front(mesh):
+        nodes, tot, tot_abs = front_face_terms(mesh)
+        dofs = 2 * nodes[:, :, None] + np.arange(2)[None, None, :]
+        rs += np.bincount(dofs.ravel(), weights=(tot_abs if absolute else np.abs(tot)).ravel(), minlength=nd)
     Jabs.sum_duplicates()
     Jabs.sort_indices()
     return rs, Jabs

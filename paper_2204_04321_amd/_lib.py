@@ -31,6 +31,7 @@ class MeshDesc(C.Structure):
         ("thickness", C.c_void_p), ("beta", C.c_void_p), ("sigma", C.c_void_p),
         ("A", C.c_double), ("n", C.c_double), ("rho", C.c_double), ("g", C.c_double),
         ("eps0", C.c_double),
+        ("front_edges", C.c_void_p), ("n_front_edges", C.c_int32), ("rho_w", C.c_double),
     ]
 
 

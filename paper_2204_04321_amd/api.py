@@ -30,8 +30,9 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 
 def mesh_desc(desc, keep: list) -> "_lib.MeshDesc":
     """fo_mesh_desc for `desc` (fields elem 'wedge' or 'hex', xy [V,2], cells [T,3|4],
-    surface, thickness, beta [V], sigma [L+1], constants A, n, rho, g, eps0).  The host
-    arrays it points to are appended to `keep`, which must outlive fo_mesh_create."""
+    surface, thickness, beta [V], sigma [L+1], constants A, n, rho, g, eps0, and optionally
+    front_edges [n,2] with rho_w).  The host arrays it points to are appended to `keep`,
+    which must outlive fo_mesh_create."""
     def arr(a, dt):
         a = np.ascontiguousarray(a, dtype=dt)
         keep.append(a)
@@ -50,6 +51,11 @@ def mesh_desc(desc, keep: list) -> "_lib.MeshDesc":
     d.sigma = arr(desc.sigma, np.float64)
     d.A, d.n, d.rho, d.g, d.eps0 = (float(desc.A), float(desc.n), float(desc.rho),
                                      float(desc.g), float(desc.eps0))
+    fe = getattr(desc, "front_edges", None)
+    if fe is not None and len(fe) > 0:
+        d.front_edges = arr(np.asarray(fe).reshape(-1, 2), np.int32)
+        d.n_front_edges = int(np.asarray(fe).reshape(-1, 2).shape[0])
+        d.rho_w = float(desc.rho_w)
     return d
 
 

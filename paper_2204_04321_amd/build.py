@@ -19,6 +19,7 @@ PROBE_LIB = os.path.join(PKG, "libfo_probe.so")   # device peak probes (measurem
 
 SOURCES = [
     "fo_mesh.cpp",
+    "fo_front.cpp",
     "fo_mesh_kernels.hip",
     "fo_assemble.hip",
     "fo_solver.hip",

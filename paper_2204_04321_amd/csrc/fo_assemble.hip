@@ -712,7 +712,12 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
         if (lane < 8 && i0 + (lane >> 1) < nvt) {
           const int u = vb + i0 + (lane >> 1);
           double *rs = Rw + slot * 2 * max_tv + 2 * (u - vb) + (lane & 1);
-          if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + (lane & 1)] = *rs;
+          double r = *rs;
+          if (m.front_slot) {   // ocean-front load of the node (memoised at upload)
+            const int fs = m.front_slot[u];
+            if (fs >= 0) r += m.front_load[(int64_t(fs) * (L + 1) + lev_k) * 2 + (lane & 1)];
+          }
+          if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + (lane & 1)] = r;
           *rs = 0.0;
         }
       }

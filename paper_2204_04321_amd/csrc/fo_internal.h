@@ -54,6 +54,10 @@ struct MeshView {
   const int32_t *slot_off; // [V] offset of v's rows inside its task's LDS level window
   const uint32_t *item_rank; // [T * nv] per item, 8 bits per corner: its rank in the
                              // item vertex's neighbour list
+  // ocean fronts: per vertex its slot in front_load (-1 if on no front); per slot and level
+  // the residual load (u, v) of the fronts on that node.  Both NULL without fronts.
+  const int32_t *front_slot; // [V]
+  const double *front_load;  // [slots][L + 1][2]
   double rho_g;            // rho * g
   double visc_pref;        // 1/2 A^(-1/n)
   double visc_exp;         // (1 - n) / (2 n)
@@ -85,6 +89,8 @@ struct fo_mesh {
   int32_t *item_vtx = nullptr;
   int32_t *slot_off = nullptr;
   uint32_t *item_rank = nullptr;
+  int32_t *front_slot = nullptr;  // ocean-front tables (NULL without fronts)
+  double *front_load = nullptr;
   int4 *tasks = nullptr;        // [n_tasks] {member, v_begin, v_end, item_begin}
   int32_t n_tasks = 0;
   std::vector<int4> tasks_host; // host copy, for building ensembles
@@ -123,6 +129,11 @@ struct EnsembleLaunch {
 };
 
 fo_status launch_ensemble(const EnsembleLaunch &E, int dtype, int kind, bool want_jac, hipStream_t s);
+
+// Ocean-front loads of a mesh description (fo_front.cpp): per vertex its slot (-1 if on no
+// front) and per slot, level and component the residual load.  Empty without fronts.
+fo_status build_front_loads(const fo_mesh_desc *d, const std::vector<double> &sigma,
+                            std::vector<int32_t> &slot, std::vector<double> &load);
 
 // Kernel launchers (fo_assemble.hip, fo_mesh_kernels.hip)
 fo_status launch_pattern(const fo_mesh *m, hipStream_t s);

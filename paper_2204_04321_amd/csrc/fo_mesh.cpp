@@ -70,7 +70,8 @@ static void free_mesh(fo_mesh *m) {
   release_events(m);
   void *ptrs[] = {m->geo, m->sb, m->colptr, m->deg, m->cells, m->rank, m->sigma,
                   m->nbr_ptr, m->nbr_idx, m->self_rank, m->vc_ptr, m->vc_idx, m->vc_pos,
-                  m->item_vtx, m->slot_off, m->item_rank, m->tasks, m->rowptr, m->colidx};
+                  m->item_vtx, m->slot_off, m->item_rank, m->tasks, m->rowptr, m->colidx,
+                  m->front_slot, m->front_load};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -134,6 +135,8 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   }
   const int32_t *C = d->base_cells;
   const double *xy = d->base_xy;
+  std::vector<int32_t> front_slot;
+  std::vector<double> front_load;
   for (int64_t t = 0; t < T; ++t) {
     for (int a = 0; a < nv; ++a) {
       const int32_t va = C[t * nv + a];
@@ -149,6 +152,11 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
       if (!(ux * wy - uy * wx > 0))
         return fail(FO_EDEGENERATE, "fo_mesh_create: cell " + std::to_string(t) + " is not counter-clockwise/convex");
     }
+  }
+
+  {
+    fo_status fst = build_front_loads(d, sig, front_slot, front_load);
+    if (fst != FO_OK) return fst;
   }
 
   // neighbour lists: vertices sharing a base cell (each vertex neighbours itself)
@@ -273,6 +281,8 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   UP(slot_off, slot_off);
   UP(item_rank, item_rank);
   UP(tasks, tasks);
+  UP(front_slot, front_slot);
+  UP(front_load, front_load);
 #undef UP
   if ((st = dev_upload(&m->cells, C, size_t(T) * nv, s)) != FO_OK) { free_mesh(m); return st; }
   if ((st = dev_upload<int64_t>(&m->rowptr, nullptr, size_t(n_dofs + 1), s)) != FO_OK) { free_mesh(m); return st; }
@@ -298,6 +308,8 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   mv.item_vtx = m->item_vtx;
   mv.slot_off = m->slot_off;
   mv.item_rank = m->item_rank;
+  mv.front_slot = m->front_slot;   // NULL without fronts (empty tables are not allocated)
+  mv.front_load = m->front_load;
   m->n_tasks = int32_t(tasks.size());
   m->tasks_host = tasks;
   m->max_slot = max_slot;
