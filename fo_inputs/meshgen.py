@@ -28,7 +28,8 @@ GRAVITY = 9.81
 
 @dataclass
 class ExtrudedMesh:
-    elem: str                 # "wedge" (triangle base) or "hex" (quadrilateral base)
+    elem: str                 # "wedge" or "tet" (triangle base: a prism, or 3 tetrahedra, per
+                              # layer) or "hex" (quadrilateral base)
     xy: np.ndarray            # [V, 2] float64, metres
     cells: np.ndarray         # [T, 3 or 4] int32, counter-clockwise base cells
     surface: np.ndarray       # [V] float64, upper-surface elevation s (m)
@@ -72,7 +73,7 @@ class ExtrudedMesh:
 
     @property
     def npe(self) -> int:
-        return 6 if self.elem == "wedge" else 8
+        return 8 if self.elem == "hex" else 6
 
     def with_fields(self, **kw) -> "ExtrudedMesh":
         return replace(self, **kw)

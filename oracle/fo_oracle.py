@@ -37,6 +37,17 @@ interpolant of nodal s differentiated with the 3D basis gradients; quadrature
 is 2x2x2 Gauss (hex) and the 3-point degree-2 triangle rule x 2-point Gauss
 (wedge); the bed measure is the physical 3D face area; reference coordinates
 lie in [0,1]; node elevations are z = (s - H) + sigma_k H with vertical columns.
+
+Tetrahedral extrusion (elem "tet", the element of the paper's nightly test, Sec. 5.3:
+3 tetrahedra per layer and base triangle): each prism is split by the global order of
+its base vertices p0 < p1 < p2 into (p0, p1, p2, p0'), (p1, p2, p0', p1'), (p2, p0', p1', p2')
+(primes: one level up), so the diagonal of every lateral quad face runs from the bottom of
+its higher-numbered vertex to the top of its lower-numbered one and neighbouring prisms
+agree.  Linear (P1) basis on each tetrahedron: gradients, strain rate and viscosity are
+constant in it, so its integrals are exact without quadrature (int phi_a = V/4).  The bed
+term is the prism's (its lower face is the first tetrahedron's face, where the P1 basis is
+the triangle's).  The CSR pattern stays the prism's: node pairs of a prism that share no
+tetrahedron are structural zeros.
 """
 from __future__ import annotations
 
@@ -196,6 +207,43 @@ def viscosity(q, A, n, eps0):
     return mu, dmu
 
 
+def tet_split(mesh, cell_ids):
+    """Prism-local node indices [nc, 3 tets, 4] of the three tetrahedra of each prism (base
+    cell index = cell_id // L), from the global order of the base triangle's vertices."""
+    tri = mesh.cells.astype(np.int64)[np.asarray(cell_ids) // mesh.n_layers]
+    p = np.argsort(tri, axis=1, kind="stable")                  # local corners by global id
+    p0, p1, p2 = p[:, 0], p[:, 1], p[:, 2]
+    return np.stack([np.stack([p0, p1, p2, p0 + 3], axis=1),
+                     np.stack([p1, p2, p0 + 3, p1 + 3], axis=1),
+                     np.stack([p2, p0 + 3, p1 + 3, p2 + 3], axis=1)], axis=1)
+
+
+def _tet_geometry(X, tets):
+    """Per prism and tetrahedron: basis gradients of the 6 prism nodes (zero for nodes not in
+    the tetrahedron) [nc, 3, 6, 3], volumes [nc, 3] and the node weights int phi_a / V
+    (1/4 on its nodes) [nc, 3, 6]."""
+    nc = X.shape[0]
+    Xl = _local(X)
+    gradN = np.zeros((nc, 3, 6, 3))
+    Nw = np.zeros((nc, 3, 6))
+    vol = np.zeros((nc, 3))
+    rows = np.arange(nc)
+    for q in range(3):
+        T = tets[:, q, :]                                         # [nc, 4]
+        X0 = Xl[rows, T[:, 0]]
+        M = np.stack([Xl[rows, T[:, j]] - X0 for j in (1, 2, 3)], axis=1)   # rows: edge vectors
+        det = np.linalg.det(M)
+        if np.any(np.abs(det) <= 0):
+            raise ValueError("degenerate tetrahedron")
+        G = np.linalg.inv(M)                                      # column j: gradient of phi_(j+1)
+        g = np.stack([-(G[:, :, 0] + G[:, :, 1] + G[:, :, 2]), G[:, :, 0], G[:, :, 1], G[:, :, 2]], axis=1)
+        for a in range(4):
+            gradN[rows, q, T[:, a], :] = g[:, a, :]
+            Nw[rows, q, T[:, a]] = 0.25
+        vol[:, q] = np.abs(det) / 6.0
+    return gradN, vol, Nw
+
+
 def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | None = None,
                    want_jac: bool = True, picard: bool = False, xyz=None, hooks=None,
                    s_drive=None, absolute: bool = False):
@@ -208,16 +256,21 @@ def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | 
     instead of the sums, the sums of the absolute values of every quadrature-point
     term (the scale of the rounding error of any summation order)."""
     ab = np.abs if absolute else (lambda x: x)
-    ref = ref or RefElement(mesh.elem)
+    tet = mesh.elem == "tet"
+    ref = ref or RefElement("wedge" if tet else mesh.elem)
     xyz = node_xyz(mesh) if xyz is None else xyz
     nodes = cell_nodes(mesh)[cell_ids]
     X = xyz[nodes]
     Ue = U.reshape(-1, 2)[nodes]
     s_vert = mesh.surface if s_drive is None else s_drive
     s_nodes = node_column_field(mesh, s_vert)[nodes]
-    gradN, W, det = _geometry(ref, X)
-    if np.any(det <= 0):
-        raise ValueError("non-positive Jacobian determinant")
+    if tet:     # three constant-gradient "points" per prism: its tetrahedra, weight = volume
+        gradN, W, Nq = _tet_geometry(X, tet_split(mesh, cell_ids))
+    else:
+        gradN, W, det = _geometry(ref, X)
+        if np.any(det <= 0):
+            raise ValueError("non-positive Jacobian determinant")
+        Nq = np.broadcast_to(ref.N, (X.shape[0],) + ref.N.shape)
     exx, eyy, exy, exz, eyz = _strain(gradN, Ue)
     q = effective_strain_rate_sq(exx, eyy, exy, exz, eyz)
     mu, dmu = viscosity(q, mesh.A, mesh.n, mesh.eps0)
@@ -231,7 +284,7 @@ def element_arrays(mesh, cell_ids: np.ndarray, U: np.ndarray, ref: RefElement | 
     sy = np.einsum("ca,cqa->cq", s_nodes, gradN[..., 1])
     grav = np.stack([sx, sy], axis=-1)                       # [nc, nq, 2]
     Re = (np.einsum("eqak->eak", ab(np.einsum("eq,eqak->eqak", W * 2 * mu, g)))
-          + rg * np.einsum("eqak->eak", ab(np.einsum("eq,qa,eqk->eqak", W, ref.N, grav))))
+          + rg * np.einsum("eqak->eak", ab(np.einsum("eq,eqa,eqk->eqak", W, Nq, grav))))
     Je = None
     if want_jac:
         gx, gy, gz = gradN[..., 0], gradN[..., 1], gradN[..., 2]
@@ -439,7 +492,7 @@ def _chunks(n, size):
 def assemble(mesh, U: np.ndarray, want_jac: bool = True, picard: bool = False,
              chunk: int = 20000, cells=None, hooks=None, s_drive=None):
     """Global residual R [n_dofs] and Jacobian (scipy CSR, summed duplicates)."""
-    ref = RefElement(mesh.elem)
+    ref = RefElement("wedge" if mesh.elem == "tet" else mesh.elem)
     xyz = node_xyz(mesh)
     nd = mesh.n_dofs
     cplx = np.iscomplexobj(U)
@@ -477,7 +530,7 @@ def _row_sums_and_matrix(mesh, U, picard, chunk, cells, absolute):
     """Sum over cells of |R_e,i| and the CSR matrix of sum over cells of |J_e,ij|, where
     R_e, J_e are the element arrays (absolute=False) or, per element, the sums of the
     absolute values of their quadrature-point terms (absolute=True)."""
-    ref = RefElement(mesh.elem)
+    ref = RefElement("wedge" if mesh.elem == "tet" else mesh.elem)
     xyz = node_xyz(mesh)
     nd = mesh.n_dofs
     rs = np.zeros(nd)
@@ -550,19 +603,24 @@ def assemble_rows(mesh, U, dofs_sel: np.ndarray, picard: bool = False):
 def energy(mesh, U, s_drive=None):
     """E(U) = sum_q W [A^(-1/n) 2n/(n+1) (q+eps0^2)^((n+1)/(2n)) + rho g grad s . (u,v)]
     + 1/2 sum_bed W^b beta (u^2 + v^2)."""
-    ref = RefElement(mesh.elem)
+    tet = mesh.elem == "tet"
+    ref = RefElement("wedge" if tet else mesh.elem)
     xyz = node_xyz(mesh)
     nodes = cell_nodes(mesh)
     X = xyz[nodes]
     Ue = U.reshape(-1, 2)[nodes]
     s_nodes = node_column_field(mesh, mesh.surface if s_drive is None else s_drive)[nodes]
-    gradN, W, _ = _geometry(ref, X)
+    if tet:
+        gradN, W, Nq = _tet_geometry(X, tet_split(mesh, np.arange(mesh.n_cells)))
+    else:
+        gradN, W, _ = _geometry(ref, X)
+        Nq = np.broadcast_to(ref.N, (X.shape[0],) + ref.N.shape)
     exx, eyy, exy, exz, eyz = _strain(gradN, Ue)
     q = effective_strain_rate_sq(exx, eyy, exy, exz, eyz)
     n = mesh.n
     dens = mesh.A ** (-1.0 / n) * (2 * n / (n + 1)) * (q + mesh.eps0 ** 2) ** ((n + 1) / (2 * n))
-    uq = np.einsum("ca,qa->cq", Ue[..., 0], ref.N)
-    vq = np.einsum("ca,qa->cq", Ue[..., 1], ref.N)
+    uq = np.einsum("ca,cqa->cq", Ue[..., 0], Nq)
+    vq = np.einsum("ca,cqa->cq", Ue[..., 1], Nq)
     sx = np.einsum("ca,cqa->cq", s_nodes, gradN[..., 0])
     sy = np.einsum("ca,cqa->cq", s_nodes, gradN[..., 1])
     E = np.sum(W * (dens + mesh.rho * mesh.g * (sx * uq + sy * vq)))

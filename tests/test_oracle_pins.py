@@ -122,7 +122,7 @@ def test_closed_form_right_wedge_n1():
 # P-2: rigid horizontal motions carry no viscous stress
 # --------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("elem", ["hex", "wedge"])
+@pytest.mark.parametrize("elem", ["hex", "wedge", "tet"])
 def test_rigid_motion_invariance(elem):
     m = _box_mesh(3, 3, 3, elem, beta=0.0)
     rng = np.random.default_rng(2)
@@ -148,7 +148,7 @@ def test_rigid_motion_invariance(elem):
 # P-3 / P-4 / P-10 / P-5: symmetry, energy, complex step, finite differences
 # --------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("elem", ["hex", "wedge"])
+@pytest.mark.parametrize("elem", ["hex", "wedge", "tet"])
 def test_symmetric_positive_definite(elem):
     m = _box_mesh(2, 2, 3, elem)
     U = smooth_velocity(m, np.random.default_rng(4), 100.0, 0.05)
@@ -159,7 +159,7 @@ def test_symmetric_positive_definite(elem):
         np.linalg.cholesky(Jd)      # raises unless SPD
 
 
-@pytest.mark.parametrize("elem", ["hex", "wedge"])
+@pytest.mark.parametrize("elem", ["hex", "wedge", "tet"])
 def test_residual_is_energy_gradient(elem):
     m = _box_mesh(3, 2, 3, elem)
     rng = np.random.default_rng(5)
@@ -175,7 +175,7 @@ def test_residual_is_energy_gradient(elem):
         assert abs(dE4 - Fv) <= 1e-7 * abs(Fv) + 1e-9 * abs(dE)
 
 
-@pytest.mark.parametrize("elem", ["hex", "wedge"])
+@pytest.mark.parametrize("elem", ["hex", "wedge", "tet"])
 def test_jacobian_complex_step(elem):
     m = _box_mesh(3, 3, 4, elem, seed=6)
     rng = np.random.default_rng(6)
@@ -225,7 +225,7 @@ def test_picard_part_drops_only_the_viscosity_derivative():
 # P-6 / P-7: linearity for n = 1, homogeneity of degree 1/n
 # --------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("elem", ["hex", "wedge"])
+@pytest.mark.parametrize("elem", ["hex", "wedge", "tet"])
 def test_n1_residual_is_affine(elem):
     m = _box_mesh(3, 2, 3, elem, seed=9).with_fields(n=1.0)
     U = smooth_velocity(m, np.random.default_rng(9), 100.0, 0.05)
@@ -274,3 +274,48 @@ def test_assemble_rows_matches_full():
     r, Jr, _ = fo.assemble_rows(m, U, sel)
     np.testing.assert_allclose(r, R[sel], rtol=1e-14, atol=0)
     assert abs(Jr - J[sel]).max() <= 1e-14 * abs(J).max()
+
+
+# --------------------------------------------------------------------------------------
+# tetrahedral extrusion: the split of each prism into three tetrahedra
+# --------------------------------------------------------------------------------------
+
+def test_tet_split_is_conforming_and_fills_the_prisms():
+    """Every triangular face of the tetrahedra is shared by exactly two of them or lies on
+    the domain boundary (bed, surface, lateral sides), so neighbouring prisms split their
+    common quad face along the same diagonal; the three tetrahedra of a prism with planar
+    lower and upper faces fill it exactly."""
+    m = _box_mesh(4, 3, 3, "tet", seed=12, pert=0.0)
+    L = m.n_layers
+    cells = np.arange(m.n_cells)
+    tets = fo.tet_split(m, cells)                           # prism-local node indices
+    nodes = fo.cell_nodes(m)[cells]
+    glob = np.take_along_axis(nodes[:, None, :].repeat(3, axis=1), tets, axis=2).reshape(-1, 4)
+    faces = {}
+    for t in glob:
+        for drop in range(4):
+            f = tuple(sorted(np.delete(t, drop)))
+            faces[f] = faces.get(f, 0) + 1
+    assert max(faces.values()) == 2
+    # faces seen once must lie on the boundary: all three nodes on the bed, on the surface,
+    # or on one lateral side of the box
+    xyz = fo.node_xyz(m)
+    lev = np.tile(np.arange(L + 1), m.n_verts)
+    xmax, ymax = m.xy[:, 0].max(), m.xy[:, 1].max()
+    col_x = np.repeat(m.xy[:, 0], L + 1)
+    col_y = np.repeat(m.xy[:, 1], L + 1)
+    for f, c in faces.items():
+        if c == 1:
+            f = list(f)
+            on = [np.all(lev[f] == 0), np.all(lev[f] == L), np.all(np.isclose(col_x[f], 0.0)),
+                  np.all(np.isclose(col_x[f], xmax)), np.all(np.isclose(col_y[f], 0.0)),
+                  np.all(np.isclose(col_y[f], ymax))]
+            assert any(on), f
+    # volumes: flat bed and surface, uniform H: every prism is a right prism
+    flat = m.with_fields(thickness=np.full(m.n_verts, 600.0), surface=np.full(m.n_verts, 900.0))
+    X = fo.node_xyz(flat)[nodes]
+    _, vol, _ = fo._tet_geometry(X, tets)
+    tri = m.xy[m.cells[cells // L]]
+    area = 0.5 * np.abs((tri[:, 1, 0] - tri[:, 0, 0]) * (tri[:, 2, 1] - tri[:, 0, 1])
+                        - (tri[:, 2, 0] - tri[:, 0, 0]) * (tri[:, 1, 1] - tri[:, 0, 1]))
+    np.testing.assert_allclose(vol.sum(axis=1), area * 600.0 / L, rtol=1e-12)

@@ -71,7 +71,7 @@ def test_scales_bound_the_entries(name, picard):
     assert np.all(EJ <= js * slack)
 
 
-@pytest.mark.parametrize("elem", ["hex", "wedge"])
+@pytest.mark.parametrize("elem", ["hex", "wedge", "tet"])
 def test_scale_equals_gravity_load_at_rest(elem):
     """U = 0 under a sloped planar surface: the strain rate vanishes, so each row of R is a
     sum of gravity terms W rho g (d_c s) N_a that all carry the sign of d_c s."""
@@ -86,13 +86,24 @@ def test_scale_equals_gravity_load_at_rest(elem):
     # split evenly over its nodes (linear basis in zeta, equal horizontal weights for the
     # box; for the wedge, every P1 triangle function integrates to area/3)
     vol = (700.0 * 400.0 if elem == "hex" else 0.5 * abs(600.0 * 500.0 - 150.0 * 100.0)) * 250.0
-    npe = 8 if elem == "hex" else 6
     rg = m.rho * m.g
-    np.testing.assert_allclose(R[0::2], rg * -0.02 * vol / npe, rtol=1e-12)
-    np.testing.assert_allclose(R[1::2], rg * 0.006 * vol / npe, rtol=1e-12)
+    if elem == "tet":
+        # the right prism splits into three tetrahedra of volume vol/3, each giving vol/12 to
+        # its 4 nodes; the lowest-numbered base vertex is in 1 of them at the bed and 3 at the
+        # top, the middle one in 2 and 2, the highest in 3 and 1
+        share = np.zeros(6)
+        order = np.argsort(m.cells[0])
+        for cnt_b, cnt_t, corner in zip((1, 2, 3), (3, 2, 1), order):
+            share[2 * corner] = cnt_b       # node v*(L+1) + 0 (bed), L = 1
+            share[2 * corner + 1] = cnt_t   # node v*(L+1) + 1 (top)
+        w = share * vol / 12.0
+    else:
+        w = np.full(m.n_dofs // 2, vol / (8 if elem == "hex" else 6))
+    np.testing.assert_allclose(R[0::2], rg * -0.02 * w, rtol=1e-12)
+    np.testing.assert_allclose(R[1::2], rg * 0.006 * w, rtol=1e-12)
 
 
-@pytest.mark.parametrize("elem", ["hex", "wedge"])
+@pytest.mark.parametrize("elem", ["hex", "wedge", "tet"])
 def test_scale_equals_bed_friction_under_translation(elem):
     """Flat surface, uniform velocity (c1, c2) with c1, c2 > 0: no strain rate, no gravity,
     each row is a sum of bed terms W beta c_c N_a N_b >= 0.  (The strain rate of a uniform

@@ -53,6 +53,28 @@ def test_exact_slab_second_order(elem):
     assert abs(ex[-2] - 101.5) < 0.5
 
 
+def test_exact_slab_tetrahedra_first_order():
+    """The same slab on tetrahedra (3 per prism): P1 on the split prism is not exact for the
+    vertical profile, and the slanted faces turn part of the vertical shear into spurious
+    horizontal strain (cross-flow v), so nodal errors and cross-flow fall at first order as
+    the layers are refined (the oracle's split and P1 gradients are what make them vanish)."""
+    errs, cross = [], []
+    for L in (4, 8, 16, 32):
+        m, s_drive, ta = _slab(L, "tet")
+        ex = _slab_exact(m, ta)
+        U0 = np.zeros(m.n_dofs)
+        U0[0::2] = 80.0
+        U, info = solve.newton_solve(m, U0, tol=1e-10, s_drive=s_drive)
+        assert info["status"] == "converged", info
+        errs.append(np.abs(U - ex).max() / np.abs(ex).max())
+        cross.append(np.abs(U[1::2]).max() / np.abs(ex).max())
+    errs, cross = np.array(errs), np.array(cross)
+    rates = np.log2(errs[:-1] / errs[1:])
+    crates = np.log2(cross[:-1] / cross[1:])
+    assert np.all(rates > 0.95) and np.all(crates > 0.95), (errs, rates, cross, crates)
+    assert errs[-1] < 4e-3 and cross[-1] < 3e-3
+
+
 # --------------------------------------------------------------------------------------
 # P-9: manufactured smooth solution, non-flat bed and surface, n = 3 with eps0,
 # lateral Dirichlet columns, volume source and top/bed tractions from the exact field
