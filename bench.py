@@ -17,6 +17,7 @@ initial guess against the shallow-ice guess on held-out ice caps (learned_vs_pla
     python bench.py --workload ensemble     # 64-member batch in one persistent launch
     python bench.py --workload newton       # Newton solves, FP64 and FP32 Jacobian values
     python bench.py --workload marine       # marine ice sheet with ocean fronts and a floating shelf
+    python bench.py --workload tet          # the ice-sheet mesh extruded to tetrahedra (3 per prism)
 """
 from __future__ import annotations
 
@@ -273,6 +274,35 @@ def marine_bench(args):
                      "algorithmic_bytes": a["alg_bytes"]}}))
 
 
+def tet_bench(args):
+    """Residual + Jacobian assembly on the ice-sheet mesh extruded to tetrahedra (3 per prism,
+    the element of the paper's nightly performance test): 7.46M tetrahedra."""
+    import torch
+
+    from fo_inputs import config1_icesheet
+    from paper_2204_04321_amd.api import Mesh
+    print("[bench] generating ice-sheet mesh (tetrahedra)", file=sys.stderr, flush=True)
+    m, U = config1_icesheet()
+    m = m.with_fields(elem="tet")
+    M = Mesh(m)
+    Ud = torch.from_numpy(U).cuda()
+    a = time_assembly(M, m, Ud, args.jdtype, args.steps, args.warmup)
+    M.close()
+    n_tets = 3 * m.n_cells
+    print(json.dumps({
+        "metric": "cells/s FO-Stokes residual+Jacobian assembly, tetrahedral extrusion (tetrahedra/s)",
+        "value": n_tets * args.steps / (a["total_ms"] / 1e3), "unit": "cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": a["ms_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.jdtype, "data": "synthetic",
+        "config": {"workload": "icesheet mesh (Delaunay of 125k seeded points in a 1500x700 km ellipse), 10 layers, "
+                               "3 tetrahedra per prism", "tetrahedra": n_tets, "prisms": m.n_cells,
+                   "dofs": M.n_dofs, "nnz": M.nnz},
+        "timing": {"median_step_ms": a["median_ms"], "consecutive_100_ms": a["ms_100"]},
+        "roofline": {"bound": "hbm", "achieved": a["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": a["achieved_gbs"] / HBM_PEAK_GBS, "kernel_ms": a["kernel_s"] * 1e3,
+                     "algorithmic_bytes": a["alg_bytes"]}}))
+
+
 def time_assembly(M, m, Ud, jdtype, steps, warmup):
     """Warm up, then time `steps` consecutive R+J assemblies between HIP events on the current
     stream, with the assembly kernel itself timed by HIP events on the library's stream.  Also
@@ -373,7 +403,7 @@ def main():
     ap.add_argument("--cpu-cells", type=int, default=200_000)
     ap.add_argument("--learned-caps", type=int, default=40)
     ap.add_argument("--marine-points", type=int, default=125_000)
-    ap.add_argument("--workload", choices=["icesheet", "ensemble", "newton", "marine"], default="icesheet",
+    ap.add_argument("--workload", choices=["icesheet", "ensemble", "newton", "marine", "tet"], default="icesheet",
                     help="icesheet: the headline single-mesh line; ensemble: the 64-member batch; "
                          "newton: Newton solves on the ice-sheet mesh with FP64 and FP32 Jacobians")
     ap.add_argument("--members", type=int, default=64)
@@ -393,6 +423,9 @@ def main():
         return
     if args.workload == "marine":
         marine_bench(args)
+        return
+    if args.workload == "tet":
+        tet_bench(args)
         return
 
     # host process pools are forked before the first device call

@@ -47,18 +47,24 @@ typedef enum {
   FO_ENOTCONV = -6       /* Newton hit its iteration cap or the line search failed */
 } fo_status;
 
-typedef enum { FO_WEDGE6 = 6, FO_HEX8 = 8 } fo_elem;     /* triangle / quad base cells */
+/* Base triangles extruded to prisms (FO_WEDGE6) or to three tetrahedra per prism (FO_TET4: the
+ * element of the paper's nightly test, Sec. 5.3; the split follows the global order of each
+ * triangle's vertices, p0 < p1 < p2: (p0,p1,p2,p0'), (p1,p2,p0',p1'), (p2,p0',p1',p2') with
+ * primes one level up, linear basis, exact integrals); base quads extruded to hexahedra
+ * (FO_HEX8).  With FO_TET4 the Jacobian keeps the prism's pattern: node pairs of a prism
+ * that share no tetrahedron are structural zeros. */
+typedef enum { FO_TET4 = 4, FO_WEDGE6 = 6, FO_HEX8 = 8 } fo_elem;
 typedef enum { FO_F64 = 0, FO_F32 = 1 } fo_dtype;         /* Jacobian value type */
 typedef enum { FO_JAC_NEWTON = 0, FO_JAC_PICARD = 1 } fo_jac_kind;
 
 /* Mesh and physical constants (Sec. 2: A, n, rho, g; beta of the sliding law). */
 typedef struct {
-  int32_t elem;              /* FO_WEDGE6 or FO_HEX8 */
+  int32_t elem;              /* FO_WEDGE6, FO_TET4 or FO_HEX8 */
   int32_t n_base_verts;      /* V >= 3 */
   int32_t n_base_cells;      /* T >= 1 */
   int32_t n_layers;          /* L >= 1 */
   const double *base_xy;     /* host [V][2], m */
-  const int32_t *base_cells; /* host [T][3 or 4], counter-clockwise, 0 <= id < V */
+  const int32_t *base_cells; /* host [T][3 or 4 (FO_HEX8)], counter-clockwise, 0 <= id < V */
   const double *surface;     /* host [V], s (m) */
   const double *thickness;   /* host [V], H > 0 (m) */
   const double *beta;        /* host [V], beta >= 0 (Pa yr / m) */

@@ -12,7 +12,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfo_stokes.so")
 
 FO_OK, FO_EINVAL, FO_ENOMEM, FO_EDEVICE, FO_EDEGENERATE, FO_ENONFINITE, FO_ENOTCONV = 0, -1, -2, -3, -4, -5, -6
-FO_WEDGE6, FO_HEX8 = 6, 8
+FO_TET4, FO_WEDGE6, FO_HEX8 = 4, 6, 8
 FO_F64, FO_F32 = 0, 1
 FO_JAC_NEWTON, FO_JAC_PICARD = 0, 1
 

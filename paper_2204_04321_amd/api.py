@@ -9,7 +9,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FO_F32, FO_F64, FO_HEX8, FO_JAC_NEWTON, FO_JAC_PICARD, FO_WEDGE6, check
+from ._lib import FO_F32, FO_F64, FO_HEX8, FO_JAC_NEWTON, FO_JAC_PICARD, FO_TET4, FO_WEDGE6, check
 
 
 def _stream(stream=None) -> int:
@@ -29,7 +29,7 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 
 
 def mesh_desc(desc, keep: list) -> "_lib.MeshDesc":
-    """fo_mesh_desc for `desc` (fields elem 'wedge' or 'hex', xy [V,2], cells [T,3|4],
+    """fo_mesh_desc for `desc` (fields elem 'wedge', 'tet' or 'hex', xy [V,2], cells [T,3|4],
     surface, thickness, beta [V], sigma [L+1], constants A, n, rho, g, eps0, and optionally
     front_edges [n,2] with rho_w).  The host arrays it points to are appended to `keep`,
     which must outlive fo_mesh_create."""
@@ -39,7 +39,7 @@ def mesh_desc(desc, keep: list) -> "_lib.MeshDesc":
         return a.ctypes.data
 
     d = _lib.MeshDesc()
-    d.elem = FO_WEDGE6 if desc.elem == "wedge" else FO_HEX8
+    d.elem = {"wedge": FO_WEDGE6, "tet": FO_TET4, "hex": FO_HEX8}[desc.elem]
     d.n_base_verts = int(desc.xy.shape[0])
     d.n_base_cells = int(desc.cells.shape[0])
     d.n_layers = int(len(desc.sigma) - 1)

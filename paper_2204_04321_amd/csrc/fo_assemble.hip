@@ -181,10 +181,129 @@ __device__ __forceinline__ void store2_nt(JT *p, double x, double y) {
   __builtin_nontemporal_store(t, reinterpret_cast<v2 *>(p));
 }
 
+// Tetrahedral extrusion: one layer of a base triangle's prism, split into three
+// tetrahedra by the global order of its corners (the corners arrive sorted, so corner r
+// has the r-th smallest vertex id): (0,1,2,0'), (1,2,0',1'), (2,0',1',2'), primes one level
+// up.  Linear basis: gradients, strain rate and viscosity are constant on a tetrahedron,
+// so every integral is exact (V times the integrand, int phi_a = V/4).  Adds the residual
+// rows of the item's two nodes (corner ra at the lower and upper level) and their
+// derivatives along the prism's 12 dofs: Jx[row level][c][d][corner][level].
+constexpr int TET_R[3][4] = {{0, 1, 2, 0}, {1, 2, 0, 1}, {2, 0, 1, 2}};   // corner of node a
+constexpr int TET_L[3][4] = {{0, 0, 0, 1}, {0, 0, 1, 1}, {0, 1, 1, 1}};   // level of node a
+
+template <class AT, bool JAC, bool N3>
+__device__ __forceinline__ void tet_layer(const MeshView &m, int ra, int picard, const double *xr, const double *yr,
+                                          const double *zlo, const double *dz, const double *ulo,
+                                          const double *du, const double *vlo, const double *dv,
+                                          const double *sv, double &Rb0, double &Rb1, double &Rt0, double &Rt1,
+                                          AT (&Jx)[2][2][2][3][2]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double X[4][3], ua[4], va[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = TET_R[q][a], l = TET_L[q][a];
+      X[a][0] = xr[r];
+      X[a][1] = yr[r];
+      X[a][2] = l ? zlo[r] + dz[r] : zlo[r];
+      ua[a] = l ? ulo[r] + du[r] : ulo[r];
+      va[a] = l ? vlo[r] + dv[r] : vlo[r];
+    }
+    // rows of M: edges from node 0; columns of M^-1 are the gradients of phi_1..3
+    double e[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) e[j][i] = X[j + 1][i] - X[0][i];
+    double cr[3][3];   // cr[j] = e[j+1] x e[j+2]
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double *p = e[(j + 1) % 3], *w = e[(j + 2) % 3];
+      cr[j][0] = p[1] * w[2] - p[2] * w[1];
+      cr[j][1] = p[2] * w[0] - p[0] * w[2];
+      cr[j][2] = p[0] * w[1] - p[1] * w[0];
+    }
+    const double det = e[0][0] * cr[0][0] + e[0][1] * cr[0][1] + e[0][2] * cr[0][2];
+    const double idet = rcp64(det);
+    double g[4][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      g[1][i] = cr[0][i] * idet;
+      g[2][i] = cr[1][i] * idet;
+      g[3][i] = cr[2][i] * idet;
+      g[0][i] = -(g[1][i] + g[2][i] + g[3][i]);
+    }
+    const double V = fabs(det) * (1.0 / 6.0);
+    double ux = 0, uy = 0, uz = 0, vx = 0, vy = 0, vz = 0, sx = 0, sy = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ux = fma(ua[a], g[a][0], ux); uy = fma(ua[a], g[a][1], uy); uz = fma(ua[a], g[a][2], uz);
+      vx = fma(va[a], g[a][0], vx); vy = fma(va[a], g[a][1], vy); vz = fma(va[a], g[a][2], vz);
+      sx = fma(sv[TET_R[q][a]], g[a][0], sx); sy = fma(sv[TET_R[q][a]], g[a][1], sy);
+    }
+    const double exx = ux, eyy = vy, exy = 0.5 * (uy + vx), exz = 0.5 * uz, eyz = 0.5 * vz;
+    const double qq = exx * exx + eyy * eyy + exx * eyy + exy * exy + exz * exz + eyz * eyz;
+    const double qe = qq + m.eps0_sq;
+    double mu;
+    if constexpr (N3) mu = m.visc_pref * rcbrt64(qe);
+    else mu = m.visc_pref * powq(qe, m.visc_exp);
+    const double s2 = 2.0 * mu * V;
+    const double t2 = picard ? 0.0 : 2.0 * (m.visc_exp * mu * rcp64(qe)) * V;
+    const double E[2][3] = {{2.0 * exx + eyy, exy, exz}, {exy, exx + 2.0 * eyy, eyz}};
+    const double gq = 0.25 * V * m.rho_g;       // rho g int phi_a / (d s)
+    // the item's two nodes: gradient on this tetrahedron (zero if not one of its nodes)
+    double gr[2][3] = {{0, 0, 0}, {0, 0, 0}}, in[2] = {0, 0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double hit = TET_R[q][a] == ra ? 1.0 : 0.0;
+      const int l = TET_L[q][a];
+      in[l] += hit;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) gr[l][i] = fma(hit, g[a][i], gr[l][i]);
+    }
+    double Rr[2][2];
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        Rr[l][c] = fma(s2, E[c][0] * gr[l][0] + E[c][1] * gr[l][1] + E[c][2] * gr[l][2],
+                       gq * in[l] * (c ? sy : sx));
+    Rb0 += Rr[0][0]; Rb1 += Rr[0][1];
+    Rt0 += Rr[1][0]; Rt1 += Rr[1][1];
+    if constexpr (JAC) {
+      const AT s2a = AT(s2), t2a = AT(t2);
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        const AT ax = AT(gr[l][0]), ay = AT(gr[l][1]), az = AT(gr[l][2]);
+        const AT Ax = s2a * ax, Ay = s2a * ay, Az = s2a * az;
+        const AT T0 = t2a * AT(E[0][0] * gr[l][0] + E[0][1] * gr[l][1] + E[0][2] * gr[l][2]);
+        const AT T1 = t2a * AT(E[1][0] * gr[l][0] + E[1][1] * gr[l][1] + E[1][2] * gr[l][2]);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int r = TET_R[q][b], lb = TET_L[q][b];
+          const AT bx = AT(g[b][0]), by = AT(g[b][1]), bz = AT(g[b][2]);
+          const AT Gu = AT(E[0][0]) * bx + AT(E[0][1]) * by + AT(E[0][2]) * bz;   // d(eps_e^2)/dU_(b,u)
+          const AT Gv = AT(E[1][0]) * bx + AT(E[1][1]) * by + AT(E[1][2]) * bz;   // d(eps_e^2)/dU_(b,v)
+          AT &uu = Jx[l][0][0][r][lb], &uv = Jx[l][0][1][r][lb];
+          AT &vu = Jx[l][1][0][r][lb], &vv = Jx[l][1][1][r][lb];
+          // K_uu = 2 ax bx + 1/2 ay by + 1/2 az bz, K_uv = ax by + 1/2 ay bx,
+          // K_vu = ay bx + 1/2 ax by, K_vv = 1/2 ax bx + 2 ay by + 1/2 az bz
+          uu = fma(Ax + Ax, bx, uu); uu = fma(AT(0.5) * Ay, by, uu); uu = fma(AT(0.5) * Az, bz, uu);
+          uu = fma(T0, Gu, uu);
+          uv = fma(Ax, by, uv); uv = fma(AT(0.5) * Ay, bx, uv); uv = fma(T0, Gv, uv);
+          vu = fma(Ay, bx, vu); vu = fma(AT(0.5) * Ax, by, vu); vu = fma(T1, Gu, vu);
+          vv = fma(AT(0.5) * Ax, bx, vv); vv = fma(Ay + Ay, by, vv); vv = fma(AT(0.5) * Az, bz, vv);
+          vv = fma(T1, Gv, vv);
+        }
+      }
+    }
+  }
+}
+
 // One wave = one task (a run of vertex columns); one lane = one (v, t) item.
 // N3 selects the n = 3 viscosity power; JAC adds the Jacobian; JT is its value type
 // (double, or float with FP32 derivative arithmetic over the FP64 primal).
-template <int NV, bool JAC, class JT, bool N3>
+template <int NV, bool JAC, class JT, bool N3, bool TET = false>
 __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, const double *__restrict__ U,
                                            double *__restrict__ R, JT *__restrict__ J, int picard,
                                            int max_slot, int max_tv, unsigned char *smem) {
@@ -212,7 +331,8 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   // rank word and the vertex ids, passed through an empty asm statement: otherwise the
   // compiler hoists the derived addresses out of the layer loop and spills them, and every
   // reload costs a scratch round trip that serialises the layer's gather loads.
-  const uint32_t imeta = uint32_t(soff) | (uint32_t(Dv) << 12) | (uint32_t(v - vb) << 20) | (uint32_t(al) << 26);
+  const uint32_t imeta_base = uint32_t(soff) | (uint32_t(Dv) << 12) | (uint32_t(v - vb) << 20);
+  const uint32_t imeta_cell = imeta_base | (uint32_t(al) << 26);
   const int slot_size = m.slot_off[ve - 1] + 12 * m.deg[ve - 1];
   // 8 bits per corner: its rank in v's neighbour list
   const uint32_t irank = act ? m.item_rank[item] : 0u;
@@ -237,6 +357,36 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
 #pragma unroll
   for (int i = 0; i < NV; ++i) vid[i] = m.cells[int64_t(t) * NV + i];
   load_geo(xl, yl, bed, Hh, su);
+  // The layer loop walks the corners in lvid order with their neighbour ranks in lrank and
+  // the item's corner al_loop: the cell's own order, or for tetrahedra the order of the
+  // vertex ids (which fixes the split of each prism).
+  int lvid[NV];
+  uint32_t lrank = irank, imeta = imeta_cell;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) lvid[i] = vid[i];
+  if constexpr (TET) {
+    int rk_of[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rk_of[i] = int(vid[i] > vid[(i + 1) % 3]) + int(vid[i] > vid[(i + 2) % 3]);
+    lrank = 0u;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      int vr = 0;
+      uint32_t br = 0u;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int hit = int(rk_of[i] == r);
+        vr += hit * vid[i];
+        br += uint32_t(hit) * ((irank >> (8 * i)) & 255u);
+      }
+      lvid[r] = vr;
+      lrank |= br << (8 * r);
+    }
+    // lanes without an item take corner 3, which no tetrahedron node has: their rows get
+    // exact zeros, so the layer loop's adds need no divergent branch (see below)
+    const int al_loop = act ? rk_of[0] * int(al == 0) + rk_of[1] * int(al == 1) + rk_of[2] * int(al == 2) : 3;
+    imeta = imeta_base | (uint32_t(al_loop) << 26);
+  }
   // P1 triangles: the horizontal basis gradients and the map determinant are constant
   double lxc[NV], lyc[NV], detc = 0, sxc = 0, syc = 0;
   if constexpr (NV == 3) {
@@ -336,10 +486,10 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
 
   for (int k = 0; k < L; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
-    uint32_t ipy = irank, imt = imeta;
+    uint32_t ipy = lrank, imt = imeta;
     int vidk[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) vidk[i] = vid[i];
+    for (int i = 0; i < NV; ++i) vidk[i] = lvid[i];
     // one statement, so that reloads of spilled operands are issued together
     if constexpr (NV == 3)
       asm volatile("" : "+v"(ipy), "+v"(imt), "+v"(vidk[0]), "+v"(vidk[1]), "+v"(vidk[2]));
@@ -348,11 +498,17 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     const int al = int(imt >> 26), soff = int(imt & 4095u), Dv = int((imt >> 12) & 255u);
     const int rloc = 2 * int((imt >> 20) & 63u);
     // gather levels k and k+1 (repeat loads hit the cache)
-    double zlo[NV], ulo[NV], vlo[NV], dz[NV], du[NV], dv[NV];
+    double zlo[NV], ulo[NV], vlo[NV], dz[NV], du[NV], dv[NV], xr[NV], yr[NV], sv[NV];
     const double s0 = m.sigma[k], s1 = m.sigma[k + 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const double4 g = m.geo[vidk[i]];
+      if constexpr (TET) {   // corner positions relative to the first, and s
+        const double4 g0 = m.geo[vidk[0]];
+        xr[i] = g.x - g0.x;
+        yr[i] = g.y - g0.y;
+        sv[i] = m.sb[vidk[i]].x;
+      }
       zlo[i] = g.z + s0 * g.w;
       dz[i] = (g.z + s1 * g.w) - zlo[i];
       const double2 a0 = *reinterpret_cast<const double2 *>(U + 2 * (int64_t(vidk[i]) * (L + 1) + k));
@@ -363,7 +519,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     }
     // wedges: x/y slopes of z, u, v at fixed zeta are (level-k sum) + zeta (increment sum)
     double HS[12];
-    if constexpr (NV == 3) {
+    if constexpr (NV == 3 && !TET) {
 #pragma unroll
       for (int h = 0; h < 12; ++h) HS[h] = 0.0;
 #pragma unroll
@@ -393,7 +549,9 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     }
 
     AT FA[2][4][2], FH[2][4][2], FB[2][4][3];
-    if constexpr (NV == 3) {
+    if constexpr (TET) {
+      tet_layer<AT, JAC, N3>(m, al, picard, xr, yr, zlo, dz, ulo, du, vlo, dv, sv, Rb0, Rb1, Rt0, Rt1, Jx);
+    } else if constexpr (NV == 3) {
       // Wedges.  The residual-only kernel runs the same loop without the tangents, so
       // both kernels produce the same residual bits.  The tangents are accumulated in
       // factorised form.  Every tangent
@@ -618,7 +776,9 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     }
 
     // ---- add v's rows into the level windows ------------------------------------------------
-    if (act) {
+    // (tetrahedra: every lane adds, lanes without an item add zeros to in-range entries; the
+    // register allocator placed spills of live values inside the branch on `act` there)
+    if (act || TET) {
       double *Rcur = Rw + cur * 2 * max_tv, *Rnxt = Rw + nxt * 2 * max_tv;
       lds_add(Rcur + rloc, Rb0);
       lds_add(Rcur + rloc + 1, Rb1);
@@ -637,7 +797,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
 #pragma unroll
           for (int cd = 0; cd < 4; ++cd) {
             const int c = cd >> 1, d = cd & 1;
-            if constexpr (NV == 3) {
+            if constexpr (NV == 3 && !TET) {
               const AT Ux = FH[a][cd][0] - FA[a][cd][0], Uy = FH[a][cd][1] - FA[a][cd][1];
 #pragma unroll
               for (int j = 0; j < NV; ++j) {
@@ -712,12 +872,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
         if (lane < 8 && i0 + (lane >> 1) < nvt) {
           const int u = vb + i0 + (lane >> 1);
           double *rs = Rw + slot * 2 * max_tv + 2 * (u - vb) + (lane & 1);
-          double r = *rs;
-          if (m.front_slot) {   // ocean-front load of the node (memoised at upload)
-            const int fs = m.front_slot[u];
-            if (fs >= 0) r += m.front_load[(int64_t(fs) * (L + 1) + lev_k) * 2 + (lane & 1)];
-          }
-          if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + (lane & 1)] = r;
+          if (R) R[2 * (int64_t(u) * (L + 1) + lev_k) + (lane & 1)] = *rs;
           *rs = 0.0;
         }
       }
@@ -729,18 +884,18 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   }
 }
 
-template <int NV, bool JAC, class JT, bool N3>
+template <int NV, bool JAC, class JT, bool N3, bool TET>
 __global__ __launch_bounds__(WAVE, NV == 3 ? 2 : 1) void owner_kernel(MeshView m, const int4 *__restrict__ tasks,
                                                      const double *__restrict__ U, double *__restrict__ R,
                                                      JT *__restrict__ J, int picard, int max_slot,
                                                      int max_tv) {
   extern __shared__ __align__(16) unsigned char smem[];
-  owner_task<NV, JAC, JT, N3>(m, tasks[blockIdx.x], U, R, J, picard, max_slot, max_tv, smem);
+  owner_task<NV, JAC, JT, N3, TET>(m, tasks[blockIdx.x], U, R, J, picard, max_slot, max_tv, smem);
 }
 
 // Persistent ensemble launch: each workgroup repeatedly takes the next (member, task) pair
 // from a device counter until the combined task table is exhausted (every wave exits).
-template <int NV, bool JAC, class JT, bool N3>
+template <int NV, bool JAC, class JT, bool N3, bool TET>
 __global__ __launch_bounds__(WAVE, NV == 3 ? 2 : 1) void ensemble_kernel(const EnsembleMember *__restrict__ mem,
                                                         const int4 *__restrict__ tasks, int n_tasks,
                                                         int *__restrict__ counter, int picard) {
@@ -754,8 +909,8 @@ __global__ __launch_bounds__(WAVE, NV == 3 ? 2 : 1) void ensemble_kernel(const E
     if (ti >= n_tasks) break;
     const int4 task = tasks[ti];
     const EnsembleMember &e = mem[task.x];
-    owner_task<NV, JAC, JT, N3>(e.view, task, e.U, e.R, static_cast<JT *>(e.J), picard, e.max_slot,
-                                e.max_tv, smem);
+    owner_task<NV, JAC, JT, N3, TET>(e.view, task, e.U, e.R, static_cast<JT *>(e.J), picard, e.max_slot,
+                                     e.max_tv, smem);
   }
 }
 
@@ -768,6 +923,17 @@ __global__ void fill_zero_kernel(uint4 *__restrict__ p, int64_t n16) {
 __global__ void fill_zero_tail_kernel(uint32_t *__restrict__ p, int64_t n4) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n4) p[i] = 0u;
+}
+
+// Ocean-front loads (memoised at upload) added to the residual rows of the front columns:
+// one thread per (front vertex, level, component).
+__global__ void front_add_kernel(int n_front, int L, const int32_t *__restrict__ vtx,
+                                 const double *__restrict__ load, double *__restrict__ R) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per = 2 * int64_t(L + 1);
+  if (i >= n_front * per) return;
+  const int64_t f = i / per, r = i - f * per;
+  R[2 * int64_t(vtx[f]) * (L + 1) + r] += load[i];
 }
 
 bool g_tables_ready[64] = {};
@@ -785,29 +951,29 @@ size_t window_bytes(bool jac, int max_slot, int max_tv) {
   return (jac ? 2 * size_t(max_slot) * sizeof(double) : 0) + 2 * 2 * size_t(max_tv) * sizeof(double);
 }
 
-template <int NV, bool JAC, class JT, bool N3>
+template <int NV, bool JAC, class JT, bool N3, bool TET>
 fo_status launch_t(const fo_mesh *mesh, const double *U, double *R, JT *J, int kind, hipStream_t s) {
   const MeshView &m = mesh->view;
   const size_t lds = window_bytes(JAC, mesh->max_slot, mesh->max_task_verts);
   fo_status st = profile_begin(mesh, s);
   if (st != FO_OK) return st;
-  hipLaunchKernelGGL((owner_kernel<NV, JAC, JT, N3>), dim3(unsigned(mesh->n_tasks)), dim3(WAVE), lds, s, m,
+  hipLaunchKernelGGL((owner_kernel<NV, JAC, JT, N3, TET>), dim3(unsigned(mesh->n_tasks)), dim3(WAVE), lds, s, m,
                      mesh->tasks, U, R, J, kind == FO_JAC_PICARD ? 1 : 0, mesh->max_slot,
                      mesh->max_task_verts);
   FO_LAUNCH_CHECK("owner_kernel");
   return profile_end(mesh, s);
 }
 
-template <int NV, bool JAC, class JT>
+template <int NV, bool JAC, class JT, bool TET = false>
 fo_status launch_n(const fo_mesh *mesh, const double *U, double *R, JT *J, int kind, hipStream_t s) {
-  if (mesh->view.n_glen == 3.0) return launch_t<NV, JAC, JT, true>(mesh, U, R, J, kind, s);
-  return launch_t<NV, JAC, JT, false>(mesh, U, R, J, kind, s);
+  if (mesh->view.n_glen == 3.0) return launch_t<NV, JAC, JT, true, TET>(mesh, U, R, J, kind, s);
+  return launch_t<NV, JAC, JT, false, TET>(mesh, U, R, J, kind, s);
 }
 
-template <int NV, bool JAC, class JT, bool N3>
+template <int NV, bool JAC, class JT, bool N3, bool TET>
 fo_status launch_ens_t(const EnsembleLaunch &E, int kind, hipStream_t s) {
   const size_t lds = window_bytes(JAC, E.max_slot, E.max_tv);
-  auto kern = ensemble_kernel<NV, JAC, JT, N3>;
+  auto kern = ensemble_kernel<NV, JAC, JT, N3, TET>;
   int per_cu = 0;
   FO_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVE, lds));
   if (per_cu < 1) per_cu = 1;
@@ -822,17 +988,32 @@ fo_status launch_ens_t(const EnsembleLaunch &E, int kind, hipStream_t s) {
   return FO_OK;
 }
 
-template <int NV, bool JAC, class JT>
+template <int NV, bool JAC, class JT, bool TET = false>
 fo_status launch_ens_n(const EnsembleLaunch &E, int kind, hipStream_t s) {
-  if (E.all_n3) return launch_ens_t<NV, JAC, JT, true>(E, kind, s);
-  return launch_ens_t<NV, JAC, JT, false>(E, kind, s);
+  if (E.all_n3) return launch_ens_t<NV, JAC, JT, true, TET>(E, kind, s);
+  return launch_ens_t<NV, JAC, JT, false, TET>(E, kind, s);
 }
 
 }  // namespace
 
+fo_status launch_front_add(const MeshView &m, int32_t n_front, const int32_t *vtx, const double *load, double *R,
+                           hipStream_t s) {
+  if (n_front == 0 || R == nullptr) return FO_OK;
+  const int64_t n = int64_t(n_front) * 2 * (m.L + 1);
+  hipLaunchKernelGGL(front_add_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, int(n_front), int(m.L), vtx,
+                     load, R);
+  FO_LAUNCH_CHECK("front_add_kernel");
+  return FO_OK;
+}
+
 fo_status launch_ensemble(const EnsembleLaunch &E, int dtype, int kind, bool want_jac, hipStream_t s) {
   fo_status st = ensure_tables(E.device);
   if (st != FO_OK) return st;
+  if (E.tet) {
+    if (!want_jac) return launch_ens_n<3, false, double, true>(E, kind, s);
+    if (dtype == FO_F32) return launch_ens_n<3, true, float, true>(E, kind, s);
+    return launch_ens_n<3, true, double, true>(E, kind, s);
+  }
   if (!want_jac) {
     if (E.nv == 3) return launch_ens_n<3, false, double>(E, kind, s);
     return launch_ens_n<4, false, double>(E, kind, s);
@@ -867,9 +1048,21 @@ fo_status launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
 
 fo_status launch_assemble(const fo_mesh *mesh, const double *U, double *R, void *J, int dtype,
                           int kind, bool want_jac, hipStream_t s) {
+  fo_status st = launch_assemble_cells(mesh, U, R, J, dtype, kind, want_jac, s);
+  if (st != FO_OK) return st;
+  return launch_front_add(mesh->view, mesh->n_front, mesh->front_vtx, mesh->front_load, R, s);
+}
+
+fo_status launch_assemble_cells(const fo_mesh *mesh, const double *U, double *R, void *J, int dtype,
+                                int kind, bool want_jac, hipStream_t s) {
   fo_status st = ensure_tables(mesh->device);
   if (st != FO_OK) return st;
   const int nv = mesh->view.nv;
+  if (mesh->view.tet) {
+    if (!want_jac) return launch_n<3, false, double, true>(mesh, U, R, nullptr, kind, s);
+    if (dtype == FO_F32) return launch_n<3, true, float, true>(mesh, U, R, static_cast<float *>(J), kind, s);
+    return launch_n<3, true, double, true>(mesh, U, R, static_cast<double *>(J), kind, s);
+  }
   if (!want_jac) {
     if (nv == 3) return launch_n<3, false, double>(mesh, U, R, nullptr, kind, s);
     return launch_n<4, false, double>(mesh, U, R, nullptr, kind, s);

@@ -41,7 +41,8 @@ extern "C" fo_status fo_ensemble_create(const fo_mesh *const *members, int32_t n
   for (int i = 0; i < n_members; ++i) {
     const fo_mesh *m = members[i];
     if (!m) return fail(FO_EINVAL, "fo_ensemble_create: NULL member");
-    if (m->view.nv != nv) return fail(FO_EINVAL, "fo_ensemble_create: members must share the element type");
+    if (m->view.nv != nv || m->view.tet != members[0]->view.tet)
+      return fail(FO_EINVAL, "fo_ensemble_create: members must share the element type");
     total += m->n_tasks;
     all_n3 = all_n3 && m->view.n_glen == 3.0;
     max_slot = std::max(max_slot, m->max_slot);
@@ -78,6 +79,7 @@ extern "C" fo_status fo_ensemble_create(const fo_mesh *const *members, int32_t n
   L.n_tasks = int32_t(tasks.size());
   L.counter = e->dev_counter;
   L.nv = nv;
+  L.tet = members[0]->view.tet != 0;
   L.all_n3 = all_n3;
   L.max_slot = max_slot;
   L.max_tv = max_tv;
@@ -118,5 +120,13 @@ extern "C" fo_status fo_ensemble_assemble(fo_ensemble *e, const double *const *U
   hipStream_t s = static_cast<hipStream_t>(stream);
   FO_HIP_TRY(hipMemcpyAsync(e->dev_members, e->staging, sizeof(EnsembleMember) * n, hipMemcpyHostToDevice, s));
   FO_HIP_TRY(hipEventRecord(e->staged, s));
-  return launch_ensemble(e->launch, dtype, kind, want_jac, s);
+  fo_status st = launch_ensemble(e->launch, dtype, kind, want_jac, s);
+  if (st != FO_OK) return st;
+  for (int i = 0; i < n; ++i) {   // members with ocean fronts: their memoised loads
+    const fo_mesh *m = e->members[i];
+    if (m->n_front > 0 && R_dev && R_dev[i] &&
+        (st = launch_front_add(m->view, m->n_front, m->front_vtx, m->front_load, R_dev[i], s)) != FO_OK)
+      return st;
+  }
+  return FO_OK;
 }

@@ -158,16 +158,16 @@ void face_integral(double len, const double zc[4], double sa, double sb, double 
 
 }  // namespace
 
-fo_status build_front_loads(const fo_mesh_desc *d, const std::vector<double> &sig, std::vector<int32_t> &slot,
+fo_status build_front_loads(const fo_mesh_desc *d, const std::vector<double> &sig, std::vector<int32_t> &vtx,
                             std::vector<double> &load) {
-  slot.clear();
+  vtx.clear();
   load.clear();
   if (d->n_front_edges == 0) return FO_OK;
   if (d->n_front_edges < 0 || !d->front_edges)
     return fail(FO_EINVAL, "fo_mesh_create: front_edges is NULL or n_front_edges < 0");
   if (!(d->rho_w > 0) || !std::isfinite(d->rho_w))
     return fail(FO_EINVAL, "fo_mesh_create: rho_w must be finite and > 0 with ocean fronts");
-  const int nv = d->elem == FO_WEDGE6 ? 3 : 4;
+  const int nv = d->elem == FO_HEX8 ? 4 : 3;
   const int64_t V = d->n_base_verts, T = d->n_base_cells, L = int64_t(sig.size()) - 1;
   // directed edges of the counter-clockwise cells
   std::map<std::pair<int32_t, int32_t>, int> dir;
@@ -190,11 +190,14 @@ fo_status build_front_loads(const fo_mesh_desc *d, const std::vector<double> &si
       return fail(FO_EINVAL, "fo_mesh_create: front edge " + std::to_string(i) + " is listed twice");
     edges.push_back(e);
   }
-  slot.assign(V, -1);
+  std::vector<int32_t> slot(V, -1);
   int32_t ns = 0;
   for (auto &e : edges)
     for (int32_t v : {e.first, e.second})
-      if (slot[v] < 0) slot[v] = ns++;
+      if (slot[v] < 0) {
+        slot[v] = ns++;
+        vtx.push_back(v);
+      }
   load.assign(size_t(ns) * (L + 1) * 2, 0.0);
   std::vector<double> gx, gw;
   gauss_legendre(16, gx, gw);

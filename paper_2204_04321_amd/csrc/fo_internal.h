@@ -32,7 +32,8 @@ fo_status fail(fo_status s, const std::string &msg);
 
 // Device-side view of one extruded mesh (plain pointers; passed by value to kernels).
 struct MeshView {
-  int32_t nv;        // vertices per base cell: 3 (wedge) or 4 (hex)
+  int32_t nv;        // vertices per base cell: 3 (wedge, tetrahedra) or 4 (hex)
+  int32_t tet;       // 1: each prism of a base triangle is split into 3 tetrahedra
   int32_t L;         // layers
   int32_t V;         // base vertices
   int32_t T;         // base cells
@@ -54,10 +55,6 @@ struct MeshView {
   const int32_t *slot_off; // [V] offset of v's rows inside its task's LDS level window
   const uint32_t *item_rank; // [T * nv] per item, 8 bits per corner: its rank in the
                              // item vertex's neighbour list
-  // ocean fronts: per vertex its slot in front_load (-1 if on no front); per slot and level
-  // the residual load (u, v) of the fronts on that node.  Both NULL without fronts.
-  const int32_t *front_slot; // [V]
-  const double *front_load;  // [slots][L + 1][2]
   double rho_g;            // rho * g
   double visc_pref;        // 1/2 A^(-1/n)
   double visc_exp;         // (1 - n) / (2 n)
@@ -89,8 +86,11 @@ struct fo_mesh {
   int32_t *item_vtx = nullptr;
   int32_t *slot_off = nullptr;
   uint32_t *item_rank = nullptr;
-  int32_t *front_slot = nullptr;  // ocean-front tables (NULL without fronts)
-  double *front_load = nullptr;
+  // ocean fronts: the vertices on a front and, per front vertex, level and component, the
+  // residual load of the fronts on that node (added after the cell assembly); NULL without
+  int32_t n_front = 0;
+  int32_t *front_vtx = nullptr;   // [n_front]
+  double *front_load = nullptr;   // [n_front][L + 1][2]
   int4 *tasks = nullptr;        // [n_tasks] {member, v_begin, v_end, item_begin}
   int32_t n_tasks = 0;
   std::vector<int4> tasks_host; // host copy, for building ensembles
@@ -122,6 +122,7 @@ struct EnsembleLaunch {
   int32_t n_tasks;
   int *counter;                    // device work counter (16 bytes)
   int32_t nv;
+  bool tet;
   bool all_n3;
   int32_t max_slot, max_tv;
   int32_t n_cu;
@@ -130,15 +131,20 @@ struct EnsembleLaunch {
 
 fo_status launch_ensemble(const EnsembleLaunch &E, int dtype, int kind, bool want_jac, hipStream_t s);
 
-// Ocean-front loads of a mesh description (fo_front.cpp): per vertex its slot (-1 if on no
-// front) and per slot, level and component the residual load.  Empty without fronts.
+// Ocean-front loads of a mesh description (fo_front.cpp): the vertices on a front and, per
+// front vertex, level and component, the residual load.  Empty without fronts.
 fo_status build_front_loads(const fo_mesh_desc *d, const std::vector<double> &sigma,
-                            std::vector<int32_t> &slot, std::vector<double> &load);
+                            std::vector<int32_t> &vtx, std::vector<double> &load);
 
 // Kernel launchers (fo_assemble.hip, fo_mesh_kernels.hip)
 fo_status launch_pattern(const fo_mesh *m, hipStream_t s);
 fo_status launch_assemble(const fo_mesh *m, const double *U, double *R, void *J, int dtype,
                           int kind, bool want_jac, hipStream_t s);
+// the cell assembly alone (launch_assemble adds the ocean-front loads after it)
+fo_status launch_assemble_cells(const fo_mesh *m, const double *U, double *R, void *J, int dtype,
+                                int kind, bool want_jac, hipStream_t s);
+fo_status launch_front_add(const MeshView &m, int32_t n_front, const int32_t *vtx, const double *load, double *R,
+                           hipStream_t s);
 fo_status launch_sia(const fo_mesh *m, double *U, hipStream_t s);
 fo_status launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 // learned initial guess (fo_learned.hip), shared with fo_newton_solve's FO_INIT_LEARNED

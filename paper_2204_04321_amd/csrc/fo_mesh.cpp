@@ -71,7 +71,7 @@ static void free_mesh(fo_mesh *m) {
   void *ptrs[] = {m->geo, m->sb, m->colptr, m->deg, m->cells, m->rank, m->sigma,
                   m->nbr_ptr, m->nbr_idx, m->self_rank, m->vc_ptr, m->vc_idx, m->vc_pos,
                   m->item_vtx, m->slot_off, m->item_rank, m->tasks, m->rowptr, m->colidx,
-                  m->front_slot, m->front_load};
+                  m->front_vtx, m->front_load};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -100,9 +100,9 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   if (!out) return fail(FO_EINVAL, "fo_mesh_create: out is NULL");
   *out = nullptr;
   if (!d) return fail(FO_EINVAL, "fo_mesh_create: desc is NULL");
-  if (d->elem != FO_WEDGE6 && d->elem != FO_HEX8)
-    return fail(FO_EINVAL, "fo_mesh_create: elem must be FO_WEDGE6 or FO_HEX8");
-  const int nv = d->elem == FO_WEDGE6 ? 3 : 4;
+  if (d->elem != FO_WEDGE6 && d->elem != FO_HEX8 && d->elem != FO_TET4)
+    return fail(FO_EINVAL, "fo_mesh_create: elem must be FO_WEDGE6, FO_TET4 or FO_HEX8");
+  const int nv = d->elem == FO_HEX8 ? 4 : 3;
   const int64_t V = d->n_base_verts, T = d->n_base_cells, L = d->n_layers;
   if (V < nv || T < 1 || L < 1) return fail(FO_EINVAL, "fo_mesh_create: need V >= 3|4, T >= 1, L >= 1");
   if (!d->base_xy || !d->base_cells || !d->surface || !d->thickness || !d->beta)
@@ -135,7 +135,7 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   }
   const int32_t *C = d->base_cells;
   const double *xy = d->base_xy;
-  std::vector<int32_t> front_slot;
+  std::vector<int32_t> front_vtx;
   std::vector<double> front_load;
   for (int64_t t = 0; t < T; ++t) {
     for (int a = 0; a < nv; ++a) {
@@ -155,7 +155,7 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   }
 
   {
-    fo_status fst = build_front_loads(d, sig, front_slot, front_load);
+    fo_status fst = build_front_loads(d, sig, front_vtx, front_load);
     if (fst != FO_OK) return fst;
   }
 
@@ -281,8 +281,9 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   UP(slot_off, slot_off);
   UP(item_rank, item_rank);
   UP(tasks, tasks);
-  UP(front_slot, front_slot);
+  UP(front_vtx, front_vtx);
   UP(front_load, front_load);
+  m->n_front = int32_t(front_vtx.size());
 #undef UP
   if ((st = dev_upload(&m->cells, C, size_t(T) * nv, s)) != FO_OK) { free_mesh(m); return st; }
   if ((st = dev_upload<int64_t>(&m->rowptr, nullptr, size_t(n_dofs + 1), s)) != FO_OK) { free_mesh(m); return st; }
@@ -290,6 +291,7 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
 
   MeshView &mv = m->view;
   mv.nv = nv;
+  mv.tet = d->elem == FO_TET4 ? 1 : 0;
   mv.L = int32_t(L);
   mv.V = int32_t(V);
   mv.T = int32_t(T);
@@ -308,8 +310,6 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
   mv.item_vtx = m->item_vtx;
   mv.slot_off = m->slot_off;
   mv.item_rank = m->item_rank;
-  mv.front_slot = m->front_slot;   // NULL without fronts (empty tables are not allocated)
-  mv.front_load = m->front_load;
   m->n_tasks = int32_t(tasks.size());
   m->tasks_host = tasks;
   m->max_slot = max_slot;

@@ -44,15 +44,13 @@ int main(int argc, char **argv) {
   d.elem = elem; d.n_base_verts = V; d.n_base_cells = T; d.n_layers = L;
   d.base_xy = xy.data(); d.base_cells = cells.data(); d.surface = s.data(); d.thickness = H.data();
   d.rho = rho; d.g = g; d.rho_w = rw; d.front_edges = fe.data(); d.n_front_edges = nfe;
-  std::vector<int32_t> slot;
+  std::vector<int32_t> vtx;
   std::vector<double> load;
-  const fo_status st = fo::build_front_loads(&d, sig, slot, load);
+  const fo_status st = fo::build_front_loads(&d, sig, vtx, load);
   if (st != FO_OK) { printf("error %d %s\n", int(st), fo::msg.c_str()); return 0; }
-  for (int v = 0; v < V; ++v)
-    if (slot[v] >= 0)
-      for (int k = 0; k <= L; ++k)
-        printf("%d %d %.17g %.17g\n", v, k, load[(size_t(slot[v]) * (L + 1) + k) * 2],
-               load[(size_t(slot[v]) * (L + 1) + k) * 2 + 1]);
+  for (size_t i = 0; i < vtx.size(); ++i)
+    for (int k = 0; k <= L; ++k)
+      printf("%d %d %.17g %.17g\n", vtx[i], k, load[(i * (L + 1) + k) * 2], load[(i * (L + 1) + k) * 2 + 1]);
   return 0;
 }
 """

@@ -31,12 +31,12 @@ TOL32 = 1e-5         # FP32 Jacobian, row scales
 TOL32_PLAIN = 1e-6   # FP32 Jacobian, norm-wise
 
 
-def _small_ellipse(seed=5, n_points=300, L=7):
+def _small_ellipse(seed=5, n_points=300, L=7, elem="wedge"):
     rng = np.random.default_rng(seed)
     a, b = 60e3, 35e3
     xy, tri = ellipse_mesh(n_points, a, b, rng)
     s, H, beta = _dome_fields(xy, a, b, rng, 2500.0, 400.0, 500.0, 1.0, 15e3, 60e3)
-    m = ExtrudedMesh("wedge", xy, tri, s, H, beta, np.linspace(0, 1, L + 1), A=1.3e-16)
+    m = ExtrudedMesh(elem, xy, tri, s, H, beta, np.linspace(0, 1, L + 1), A=1.3e-16)
     return m, dome_velocity(m, a, b, rng, 200.0)
 
 
@@ -56,7 +56,7 @@ def _graded_sigma(m):
     return m.with_fields(sigma=sg)
 
 
-def _fan(n_cells=64, L=3, seed=8):
+def _fan(n_cells=64, L=3, seed=8, elem="wedge"):
     """One vertex in n_cells triangles (64 is the per-vertex maximum), ring vertices with 2 or 3 cells."""
     rng = np.random.default_rng(seed)
     ang = np.sort(rng.uniform(0, 2 * np.pi, n_cells))
@@ -65,7 +65,7 @@ def _fan(n_cells=64, L=3, seed=8):
     cells = np.array([[0, 1 + i, 1 + (i + 1) % n_cells] for i in range(n_cells)], dtype=np.int32)
     V = xy.shape[0]
     H = 600 + 100 * rng.uniform(size=V)
-    m = ExtrudedMesh("wedge", xy, cells, 200 - 0.01 * xy[:, 0] + H, H, 400 + 300 * rng.uniform(size=V),
+    m = ExtrudedMesh(elem, xy, cells, 200 - 0.01 * xy[:, 0] + H, H, 400 + 300 * rng.uniform(size=V),
                      np.linspace(0, 1, L + 1))
     return m, smooth_velocity(m, rng, 60.0, 0.05)
 
@@ -107,6 +107,14 @@ CASES = {
     "fan_64_cells_at_a_vertex": lambda: _fan(),
     "ellipse_wedge_20_layers": lambda: _small_ellipse(seed=12, n_points=200, L=20),
     "free_slip_patch": lambda: _free_slip_patch(),
+    # tetrahedral extrusion: 3 tetrahedra per prism, split by the global vertex order
+    "tet_box_pert": lambda: _box(5, 4, 3, "tet", 15),
+    "tet_ellipse_ragged": lambda: _small_ellipse(seed=16, n_points=250, L=6, elem="tet"),
+    "tet_single_layer": lambda: _box(4, 3, 1, "tet", 17),
+    "tet_graded_sigma": lambda: (lambda mu: (_graded_sigma(mu[0]), mu[1]))(_box(3, 4, 5, "tet", 18)),
+    "tet_fan_64_cells": lambda: _fan(elem="tet"),
+    "tet_glen_n1": lambda: (lambda mu: (mu[0].with_fields(n=1.0, A=2e-13), mu[1]))(_box(4, 3, 3, "tet", 19)),
+    "tet_glen_n4": lambda: (lambda mu: (mu[0].with_fields(n=4.0, A=1e-20), mu[1]))(_box(4, 4, 3, "tet", 20)),
     # ocean back-pressure on marked lateral fronts; floating ice has beta = 0
     "ocean_front_slab_hex": lambda: _float_slab("hex"),
     "ocean_front_slab_wedge_steep": lambda: _float_slab("wedge", steep=True),

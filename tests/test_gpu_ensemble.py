@@ -135,3 +135,37 @@ def test_wedge_ensemble_with_general_exponent():
             e = parity_errors(R.cpu().numpy(), Jg, Ro, Jo, fo.abs_scales(m, U), fo.element_scales(m, U))
             assert e["term"][0] <= 1e-12 and e["elem"][0] <= 1e-12 and e["plain"][0] <= 1e-12, (dtype, e)
             assert e["term"][1] <= tol and e["elem"][1] <= tol and e["plain"][1] <= tol_plain, (dtype, e)
+
+
+def test_tetrahedral_ensemble_with_fronts_equals_single_mesh():
+    """Tetrahedral members, one of them with ocean fronts: the persistent launch and the
+    front loads added after it give each member's single-mesh result bit for bit; a wedge
+    member in the same ensemble is refused (one element type per launch)."""
+    from fo_inputs import marine_sheet
+    from test_gpu_assembly import _box
+    from paper_2204_04321_amd import _lib
+    from paper_2204_04321_amd.api import Ensemble
+    mar, Umar = marine_sheet(seed=8, n_points=300, n_layers=4)
+    tets = [_box(nx, ny, L, "tet", 60 + i) for i, (nx, ny, L) in enumerate([(3, 2, 2), (8, 6, 5)])]
+    tets.append((mar.with_fields(elem="tet"), Umar))
+    Ms = [gpu_mesh(m) for m, _ in tets]
+    E = Ensemble(Ms)
+    Us = [to_dev(U) for _, U in tets]
+    for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        Rs = [torch.full((M.n_dofs,), float("nan"), dtype=torch.float64, device="cuda") for M in Ms]
+        Js = [torch.full((M.nnz,), float("nan"), dtype=tdt, device="cuda") for M in Ms]
+        E.assemble(Us, Rs, Js, dtype=dtype)
+        torch.cuda.synchronize()
+        for M, Ud, R, J in zip(Ms, Us, Rs, Js):
+            R1, J1 = M.jacobian(Ud, dtype=dtype)
+            torch.cuda.synchronize()
+            assert torch.equal(R, R1) and torch.equal(J, J1)
+    (m, U), M = tets[-1], Ms[-1]
+    R1, J1 = gpu_jacobian(M, U)
+    Ro, Jo = fo.assemble(m, U)
+    e = parity_errors(R1, J1, Ro, Jo, fo.abs_scales(m, U), fo.element_scales(m, U))
+    print(f"\n[tet ensemble, marine member] {e}")
+    assert max(e["term"]) <= 1e-12 and max(e["elem"]) <= 1e-12 and max(e["plain"]) <= 1e-12
+    w, _ = _box(3, 2, 2, "wedge", 70)
+    with pytest.raises(_lib.FoError):
+        Ensemble([Ms[0], gpu_mesh(w)])

@@ -65,6 +65,27 @@ def test_newton_pcg_matches_oracle_solution(cap, jdt):
     assert diff <= 1e-6
 
 
+@pytest.mark.parametrize("jdt", ["f64", "f32"])
+def test_newton_tetrahedra_match_oracle_solution(jdt):
+    """A cap extruded to tetrahedra (3 per prism): Newton from the shallow-ice guess against
+    the oracle's direct-solve Newton on the same discretisation."""
+    m = _cap(seed=21, n_points=300, L=5)
+    m = m.with_fields(elem="tet")
+    U_ref, info = solve.newton_solve(m, solve.sia_guess(m), tol=1e-11)
+    assert info["status"] == "converged", info
+    M = gpu_mesh(m)
+    U = to_dev(solve.sia_guess(m))
+    rep = M.newton_solve(U, tol=1e-8, jac_dtype=jdt)
+    print(f"\n[newton tet {jdt}] its {rep['newton_its']} gmres {rep['lin_its']} res {rep['final_rel']:.2e}")
+    assert rep["status"] == 0, rep
+    Ug = U.cpu().numpy()
+    f0 = np.linalg.norm(fo.residual(m, np.zeros_like(Ug)))
+    assert np.linalg.norm(fo.residual(m, Ug)) <= 1.01e-8 * f0
+    diff = np.abs(Ug - U_ref).max() / np.abs(U_ref).max()
+    print(f"[newton tet {jdt}] max |U - U_oracle| / max |U_oracle| = {diff:.2e}")
+    assert diff <= 1e-6
+
+
 def test_newton_marine_sheet_with_ocean_fronts():
     """Marine ice sheet: grounded interior, a floating shelf (beta = 0) and ocean fronts on
     its seaward boundary.  Newton from the shallow-ice guess against the oracle's
