@@ -209,19 +209,28 @@ def newton_bench(args):
     import torch
 
     from fo_inputs import config1_icesheet
-    from paper_2204_04321_amd.api import Mesh
+    from paper_2204_04321_amd.api import Mdsc, Mesh
     print("[bench] generating ice-sheet mesh", file=sys.stderr, flush=True)
     m, _ = config1_icesheet()
     M = Mesh(m)
     U = torch.zeros(M.n_dofs, dtype=torch.float64, device="cuda")
+    prec = {}
+    mdsc_setup_ms = None
+    if args.precond == "mdsc":
+        t0 = time.perf_counter()
+        P = Mdsc(M)
+        mdsc_setup_ms = (time.perf_counter() - t0) * 1e3
+        prec = {"preconditioner": "mdsc", "mdsc": P}
+        print(f"[bench] two-level preconditioner: plane levels {P.level_verts}, created in {mdsc_setup_ms:.0f} ms",
+              file=sys.stderr, flush=True)
     for jdt in ("f64", "f32"):
         opts = M.newton_opts(jac_dtype=jdt)
         ws = torch.empty(M.workspace_bytes(opts), dtype=torch.uint8, device="cuda")
         lin = args.linear_solver
-        M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt, max_newton=1, linear_solver=lin)   # first call
+        M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt, max_newton=1, linear_solver=lin, **prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep = M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt, linear_solver=lin)
+        rep = M.newton_solve(U, workspace=ws, init="sia", jac_dtype=jdt, linear_solver=lin, **prec)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         print(f"[bench] newton {jdt}: status {rep['status']} its {rep['newton_its']} {lin} {rep['lin_its']} "
@@ -232,8 +241,11 @@ def newton_bench(args):
             "dtype": "f64 (Jacobian values " + jdt + ")", "data": "synthetic",
             "config": {"workload": "icesheet wedge mesh, 2,487,040 wedges, 2,750,000 dofs; "
                                    + ("GMRES(100)" if lin == "gmres" else "conjugate gradients")
-                                   + " with vertical-column block-LU preconditioner, lin_rtol 1e-6, <= 500 its/step",
-                       "jacobian_values": jdt, "linear_solver": lin},
+                                   + (" with vertical-column block-LU preconditioner" if args.precond == "column"
+                                      else " with the two-level column semicoarsening preconditioner")
+                                   + ", lin_rtol 1e-6, <= 500 its/step",
+                       "jacobian_values": jdt, "linear_solver": lin, "preconditioner": args.precond,
+                       "mdsc_create_ms": mdsc_setup_ms},
             "status": rep["status"], "newton_its": rep["newton_its"],
             ("gmres_its" if lin == "gmres" else "cg_its"): rep["lin_its"],
             "residual_calls": rep["residual_calls"], "jacobian_calls": rep["jacobian_calls"],
@@ -409,6 +421,8 @@ def main():
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--linear-solver", choices=["gmres", "pcg"], default="gmres",
                     help="Newton workload: GMRES (the paper's) or conjugate gradients")
+    ap.add_argument("--precond", choices=["column", "mdsc"], default="column",
+                    help="Newton workload: column block-LU or the two-level semicoarsening preconditioner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "

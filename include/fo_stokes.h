@@ -147,6 +147,12 @@ typedef enum { FO_INIT_USER = 0, FO_INIT_SIA = 1, FO_INIT_LEARNED = 2 } fo_init;
  * requirement). */
 typedef enum { FO_LIN_GMRES = 0, FO_LIN_PCG = 1 } fo_linear_solver;
 
+/* Preconditioner of each Newton step's linear system.  FO_PREC_COLUMN: block LU of each vertical
+ * column (block Jacobi over columns).  FO_PREC_MDSC: the two-level column semicoarsening
+ * preconditioner of a fo_mdsc object (see fo_mdsc_create), GMRES only. */
+typedef enum { FO_PREC_COLUMN = 0, FO_PREC_MDSC = 1 } fo_preconditioner;
+typedef struct fo_mdsc fo_mdsc;
+
 typedef struct {
   double tol;              /* stop when ||F(U)||_2 <= tol ||F(0)||_2 (default 1e-8) */
   int32_t max_newton;      /* Newton iteration cap (50) */
@@ -162,6 +168,10 @@ typedef struct {
   const float *mlp_norm;   /* FO_INIT_LEARNED: device [20] feature means then standard deviations */
   int32_t learned_fallback;/* FO_INIT_LEARNED: fallback rule of fo_initial_guess_learned (1) */
   int32_t learned_smooth;  /* FO_INIT_LEARNED: smoothing sweeps of fo_initial_guess_learned (0) */
+  int32_t preconditioner;  /* fo_preconditioner (FO_PREC_COLUMN) */
+  fo_mdsc *mdsc;           /* FO_PREC_MDSC: a preconditioner object created on this mesh; each Newton
+                              step runs fo_mdsc_setup on its Jacobian, so its previous numeric
+                              state is overwritten */
 } fo_newton_opts;
 
 typedef struct {
@@ -193,7 +203,8 @@ void fo_newton_default_opts(fo_newton_opts *opts);
 size_t fo_newton_workspace_bytes(const fo_mesh *mesh, const fo_newton_opts *opts);
 
 /* Damped Newton with GMRES(restart) right-preconditioned by block LU of each vertical
- * column's 2(L+1) x 2(L+1) block (block-tridiagonal, no pivoting) and a backtracking
+ * column's 2(L+1) x 2(L+1) block (block-tridiagonal, no pivoting; or, with FO_PREC_MDSC,
+ * the two-level preconditioner built on those column factors) and a backtracking
  * line search (alpha = 1, 1/2, ... accepting a decrease by (1 - 1e-4 alpha)).  U_dev
  * [n_dofs] holds the initial guess (unless init = FO_INIT_SIA) and returns the last
  * accepted iterate.  workspace_dev: caller-owned device memory, 256-byte aligned, at
@@ -202,6 +213,69 @@ size_t fo_newton_workspace_bytes(const fo_mesh *mesh, const fo_newton_opts *opts
 fo_status fo_newton_solve(const fo_mesh *mesh, double *U_dev, const fo_newton_opts *opts,
                           fo_newton_report *report, void *workspace_dev, size_t workspace_bytes,
                           void *stream);
+
+/* ---- Two-level column semicoarsening preconditioner (Sec. 3.3, Sec. 4.4) ---------------------
+ * The paper preconditions GMRES by multigrid that coarsens the extruded mesh vertically with
+ * a matrix-dependent prolongator, built per vertical line from that line's block-tridiagonal
+ * system solved by LU without pivoting, down to one layer, and then runs aggregation AMG on
+ * the plane with Chebyshev smoothing.  This object implements that design in two levels:
+ *   smoother B:   block LU (no pivoting, FP64 recursion, FP32 factors) of every vertex
+ *                 column's block-tridiagonal 2(L+1) x 2(L+1) block;
+ *   collapse P0:  per column v and component c the weights w = B_v^-1 e_c (e_c: 1 at
+ *                 component c of every level), FP64, scaled so the mean of the component-c
+ *                 entries is 1 (e_c itself where that mean is not a positive finite number);
+ *   plane:        A_0 = P0^T J P0, 2 dofs per base vertex on the base-mesh graph (vertices
+ *                 that share a base cell), aggregated level by level until at most 64
+ *                 vertices remain (pass 1 in index order: a vertex whose neighbours are all
+ *                 unassigned roots an aggregate of itself and its neighbours, isolated
+ *                 vertices are grouped 8 at a time; pass 2: every vertex left joins the
+ *                 aggregate of its lowest-numbered neighbour assigned in pass 1), unsmoothed
+ *                 transfers, Galerkin operators, Chebyshev degree 2 over [g/30, g] on
+ *                 D^-1 A (D: 2x2 diagonal blocks, g: the Gershgorin bound max row sum of
+ *                 |D^-1 A|) before and after the coarse correction, the coarsest level
+ *                 solved by its inverse (Gauss-Jordan with partial pivoting);
+ *   application:  y = V-cycle(P0^T r), z = P0 y + B^-1 (r - J P0 y).
+ * All device memory is allocated by fo_mdsc_create and owned by the object; the mesh must
+ * outlive it.  Calls on one object must not overlap. */
+
+/* Host-side aggregation of a graph: n vertices, sorted neighbour lists ptr [n+1], idx
+ * (each containing the vertex itself), into agg [n] (host) and *n_agg, by the two passes
+ * above.  Pure host code, no device needed.  FO_EINVAL on a malformed graph. */
+fo_status fo_mdsc_aggregate_graph(int32_t n, const int32_t *ptr, const int32_t *idx, int32_t *agg,
+                                  int32_t *n_agg);
+
+/* Build the hierarchy's graphs, aggregates and transfer tables for a mesh (host work plus
+ * device allocations; about 4(L+1)(2 nnz_plane + 3 V) doubles, nnz_plane the number of
+ * base-vertex pairs that share a cell).  Synchronises `stream`. */
+fo_status fo_mdsc_create(const fo_mesh *mesh, void *stream, fo_mdsc **out);
+void fo_mdsc_destroy(fo_mdsc *p);
+
+/* Plane levels: *n_levels smoothed levels plus the coarsest; n_verts (may be NULL) receives
+ * n_levels + 1 vertex counts, level 0 being the base mesh. */
+fo_status fo_mdsc_levels(const fo_mdsc *p, int32_t *n_levels, int32_t *n_verts);
+
+/* Host copies of level `level`'s graph (ptr [n+1], idx [ptr[n]]; either may be NULL) and, for
+ * a smoothed level, of its aggregate map agg [n] (may be NULL; FO_EINVAL on the coarsest). */
+fo_status fo_mdsc_graph(const fo_mdsc *p, int32_t level, int32_t *ptr, int32_t *idx, int32_t *agg);
+
+/* Numeric setup from a Jacobian J_dev [nnz] of `jac_dtype` (FO_F64 or FO_F32), in the
+ * library's Jacobian layout: column factors, weights, J P0, the plane operators, their
+ * diagonal inverses and bounds, and the coarsest inverse.  Synchronises `stream` (one
+ * status read); FO_ENONFINITE if a diagonal block or the coarsest operator is singular or
+ * not finite. */
+fo_status fo_mdsc_setup(fo_mdsc *p, const void *J_dev, int32_t jac_dtype, void *stream);
+
+/* z_dev = M^-1 r_dev (FP64 [n_dofs] each, distinct, 16-byte aligned) after fo_mdsc_setup.
+ * A fixed linear operator (right preconditioning); asynchronous on `stream`. */
+fo_status fo_mdsc_apply(const fo_mdsc *p, const double *r_dev, double *z_dev, void *stream);
+
+/* Copy numeric setup to the host: what = FO_MDSC_WEIGHTS (level ignored): the weights
+ * [V][L+1][2 c'][2 c] (count V (L+1) 4); FO_MDSC_PLANE: level `level`'s block values in its
+ * graph order, block [2 c + d] (count 4 ptr[n]); FO_MDSC_BOUND: the Gershgorin bound of a
+ * smoothed level (count 1).  Synchronises `stream`. */
+typedef enum { FO_MDSC_WEIGHTS = 0, FO_MDSC_PLANE = 1, FO_MDSC_BOUND = 2 } fo_mdsc_field;
+fo_status fo_mdsc_export(const fo_mdsc *p, int32_t what, int32_t level, double *host, size_t count,
+                         void *stream);
 
 /* ---- Batched ensembles (many meshes, one persistent launch) ---------------------------- */
 typedef struct fo_ensemble fo_ensemble;

@@ -7,7 +7,7 @@ from ._lib import FoError  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("Mesh", "Ensemble"):
+    if name in ("Mesh", "Ensemble", "Mdsc", "aggregate_graph"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

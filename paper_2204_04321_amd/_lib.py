@@ -41,7 +41,7 @@ class NewtonOpts(C.Structure):
         ("gmres_restart", C.c_int32), ("max_lin", C.c_int32), ("jac_dtype", C.c_int32),
         ("max_backtracks", C.c_int32), ("init", C.c_int32), ("linear_solver", C.c_int32),
         ("mlp_params", C.c_void_p), ("mlp_norm", C.c_void_p), ("learned_fallback", C.c_int32),
-        ("learned_smooth", C.c_int32),
+        ("learned_smooth", C.c_int32), ("preconditioner", C.c_int32), ("mdsc", C.c_void_p),
     ]
 
 
@@ -64,6 +64,8 @@ class NewtonReport(C.Structure):
 
 FO_INIT_USER, FO_INIT_SIA, FO_INIT_LEARNED = 0, 1, 2
 FO_LIN_GMRES, FO_LIN_PCG = 0, 1
+FO_PREC_COLUMN, FO_PREC_MDSC = 0, 1
+FO_MDSC_WEIGHTS, FO_MDSC_PLANE, FO_MDSC_BOUND = 0, 1, 2
 
 _lib = None
 
@@ -98,6 +100,14 @@ def _declare(lib):
         "fo_initial_guess_learned_noalloc": (C.c_int, [vp, vp, vp, vp, i32, i32, C.POINTER(C.c_int32), vp]),
         "fo_learned_targets": (C.c_int, [vp, vp, vp, vp, vp]),
         "fo_feature_stats": (C.c_int, [vp, C.c_int64, vp, vp, vp]),
+        "fo_mdsc_aggregate_graph": (C.c_int, [i32, vp, vp, vp, C.POINTER(C.c_int32)]),
+        "fo_mdsc_create": (C.c_int, [vp, vp, C.POINTER(vp)]),
+        "fo_mdsc_destroy": (None, [vp]),
+        "fo_mdsc_levels": (C.c_int, [vp, C.POINTER(C.c_int32), vp]),
+        "fo_mdsc_graph": (C.c_int, [vp, i32, vp, vp, vp]),
+        "fo_mdsc_setup": (C.c_int, [vp, vp, i32, vp]),
+        "fo_mdsc_apply": (C.c_int, [vp, vp, vp, vp]),
+        "fo_mdsc_export": (C.c_int, [vp, i32, i32, vp, C.c_size_t, vp]),
         "fo_status_string": (C.c_char_p, [C.c_int]),
         "fo_last_error": (C.c_char_p, []),
     }

@@ -138,6 +138,10 @@ class Mesh:
                 v = _ptr(v) if isinstance(v, torch.Tensor) else v
             elif k == "linear_solver":
                 v = {"gmres": _lib.FO_LIN_GMRES, "pcg": _lib.FO_LIN_PCG}.get(v, v)
+            elif k == "preconditioner":
+                v = {"column": _lib.FO_PREC_COLUMN, "mdsc": _lib.FO_PREC_MDSC}.get(v, v)
+            elif k == "mdsc":
+                v = v.handle.value if isinstance(v, Mdsc) else v
             setattr(o, k, v)
         return o
 
@@ -220,6 +224,78 @@ class Mesh:
     def _check_vec(self, U):
         if U.dtype != torch.float64 or U.numel() != self.n_dofs:
             raise ValueError(f"expected float64 vector of {self.n_dofs} dofs")
+
+
+def aggregate_graph(ptr: np.ndarray, idx: np.ndarray):
+    """Host aggregation of a graph given as sorted neighbour lists (with the vertex itself):
+    returns (agg [n] int32, n_agg).  No device needed."""
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    n = len(ptr) - 1
+    agg = np.empty(max(n, 0), dtype=np.int32)
+    n_agg = C.c_int32()
+    check(_lib.lib().fo_mdsc_aggregate_graph(n, ptr.ctypes.data, idx.ctypes.data, agg.ctypes.data, C.byref(n_agg)))
+    return agg, n_agg.value
+
+
+class Mdsc:
+    """Two-level column semicoarsening preconditioner of one mesh (the library object)."""
+
+    def __init__(self, mesh: Mesh, stream=None):
+        self.mesh = mesh
+        h = C.c_void_p()
+        check(_lib.lib().fo_mdsc_create(mesh.handle, _stream(stream), C.byref(h)))
+        self.handle = h
+        nl = C.c_int32()
+        check(_lib.lib().fo_mdsc_levels(h, C.byref(nl), None))
+        nv = np.empty(nl.value + 1, dtype=np.int32)
+        check(_lib.lib().fo_mdsc_levels(h, C.byref(nl), nv.ctypes.data))
+        self.n_levels = nl.value
+        self.level_verts = [int(x) for x in nv]
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lib().fo_mdsc_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def graph(self, level: int):
+        """(ptr, idx, agg) of a plane level (agg None on the coarsest)."""
+        n = self.level_verts[level]
+        ptr = np.empty(n + 1, dtype=np.int32)
+        check(_lib.lib().fo_mdsc_graph(self.handle, level, ptr.ctypes.data, None, None))
+        idx = np.empty(int(ptr[-1]), dtype=np.int32)
+        agg = np.empty(n, dtype=np.int32) if level < self.n_levels else None
+        check(_lib.lib().fo_mdsc_graph(self.handle, level, None, idx.ctypes.data,
+                                       agg.ctypes.data if agg is not None else None))
+        return ptr, idx, agg
+
+    def setup(self, Jvals: torch.Tensor, stream=None):
+        dt = FO_F64 if Jvals.dtype == torch.float64 else FO_F32
+        check(_lib.lib().fo_mdsc_setup(self.handle, _ptr(Jvals), dt, _stream(stream)))
+
+    def apply(self, r: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        self.mesh._check_vec(r)
+        z = out if out is not None else torch.empty_like(r)
+        check(_lib.lib().fo_mdsc_apply(self.handle, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def export(self, what: str, level: int = 0, stream=None) -> np.ndarray:
+        field = {"weights": _lib.FO_MDSC_WEIGHTS, "plane": _lib.FO_MDSC_PLANE, "bound": _lib.FO_MDSC_BOUND}[what]
+        if field == _lib.FO_MDSC_WEIGHTS:
+            n = 4 * self.mesh.n_nodes
+        elif field == _lib.FO_MDSC_PLANE:
+            n = 4 * int(self.graph(level)[0][-1])
+        else:
+            n = 1
+        out = np.empty(n, dtype=np.float64)
+        check(_lib.lib().fo_mdsc_export(self.handle, field, level, out.ctypes.data, n, _stream(stream)))
+        return out
 
 
 class Ensemble:

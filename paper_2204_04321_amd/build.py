@@ -26,6 +26,8 @@ SOURCES = [
     "fo_newton.cpp",
     "fo_ensemble.cpp",
     "fo_learned.hip",
+    "fo_mdsc_host.cpp",
+    "fo_mdsc.hip",
 ]
 
 ARCH = "gfx950"

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "fo_internal.h"
+#include "fo_mdsc.h"
 #include "fo_solver.h"
 
 namespace fo {
@@ -77,6 +78,12 @@ fo_status norm2(Ctx &c, const double *x, double &out) {
   return FO_OK;
 }
 
+// z = M^{-1} r with the preconditioner the options name
+fo_status precondition(Ctx &c, const fo_newton_opts *o, const double *r, double *z) {
+  if (o->preconditioner == FO_PREC_MDSC) return fo_mdsc_apply(o->mdsc, r, z, c.s);
+  return colblock_apply(c.m, reinterpret_cast<const float *>(c.ws + c.L.fac), r, z, c.s);
+}
+
 // GMRES(m), right preconditioned: solve J x = b, x0 = 0.  Returns iterations in `its`.
 fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b, double *x, int64_t &its,
                 double &rel_out) {
@@ -86,7 +93,6 @@ fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b
   double *w = c.dptr(c.L.W);
   double *z = c.dptr(c.L.Z);
   double *t = c.dptr(c.L.T);
-  float *fac = reinterpret_cast<float *>(c.ws + c.L.fac);
   fo_status st;
   its = 0;
   double bnorm;
@@ -107,7 +113,7 @@ fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b
     int jend = -1;
     for (int j = 0; j < mres; ++j) {
       double *vj = V + int64_t(j) * n;
-      if ((st = colblock_apply(c.m, fac, vj, z, c.s)) != FO_OK) return st;
+      if ((st = precondition(c, o, vj, z)) != FO_OK) return st;
       if ((st = spmv(c.m, Jv, o->jac_dtype, z, w, c.s)) != FO_OK) return st;
       // classical Gram-Schmidt with one selective reorthogonalisation.  A pass that
       // shrinks w by kappa = ||w|| / ||w - V h|| leaves it orthogonal to V only to about
@@ -165,7 +171,7 @@ fo_status gmres(Ctx &c, const fo_newton_opts *o, const void *Jv, const double *b
     FO_HIP_TRY(hipMemcpyAsync(c.dptr(c.L.dots), c.host, sizeof(double) * k, hipMemcpyHostToDevice, c.s));
     if ((st = launch_fill_zero(t, sizeof(double) * n, c.s)) != FO_OK) return st;
     if ((st = multiaxpy(n, V, n, k, c.dptr(c.L.dots), t, 1.0, c.s)) != FO_OK) return st;
-    if ((st = colblock_apply(c.m, fac, t, z, c.s)) != FO_OK) return st;
+    if ((st = precondition(c, o, t, z)) != FO_OK) return st;
     if ((st = axpby(n, 1.0, z, 1.0, x, c.s)) != FO_OK) return st;
     if (!done) {
       // restart: r = b - J x
@@ -259,6 +265,8 @@ extern "C" void fo_newton_default_opts(fo_newton_opts *o) {
   o->mlp_norm = nullptr;
   o->learned_fallback = 1;
   o->learned_smooth = 0;
+  o->preconditioner = FO_PREC_COLUMN;
+  o->mdsc = nullptr;
 }
 
 extern "C" size_t fo_newton_workspace_bytes(const fo_mesh *m, const fo_newton_opts *o) {
@@ -274,8 +282,15 @@ extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newto
       (o->jac_dtype != FO_F64 && o->jac_dtype != FO_F32) ||
       (o->init != FO_INIT_USER && o->init != FO_INIT_SIA && o->init != FO_INIT_LEARNED) ||
       (o->init == FO_INIT_LEARNED && (!o->mlp_params || !o->mlp_norm)) ||
-      (o->linear_solver != FO_LIN_GMRES && o->linear_solver != FO_LIN_PCG))
+      (o->linear_solver != FO_LIN_GMRES && o->linear_solver != FO_LIN_PCG) ||
+      (o->preconditioner != FO_PREC_COLUMN && o->preconditioner != FO_PREC_MDSC))
     return fail(FO_EINVAL, "fo_newton_solve: bad options");
+  if (o->preconditioner == FO_PREC_MDSC) {
+    if (!o->mdsc || o->mdsc->mesh != m)
+      return fail(FO_EINVAL, "fo_newton_solve: FO_PREC_MDSC needs a fo_mdsc created on this mesh");
+    if (o->linear_solver != FO_LIN_GMRES)
+      return fail(FO_EINVAL, "fo_newton_solve: FO_PREC_MDSC is not symmetric; use FO_LIN_GMRES");
+  }
   if ((reinterpret_cast<uintptr_t>(U) & 15) || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(FO_EINVAL, "fo_newton_solve: U must be 16-byte and workspace 256-byte aligned");
   Ctx c;
@@ -339,7 +354,11 @@ extern "C" fo_status fo_newton_solve(const fo_mesh *m, double *U, const fo_newto
     rep->jacobian_calls++;
     // Preconditioner Construction
     t0 = std::chrono::steady_clock::now();
-    if ((st = colblock_factor(m, Jv, o->jac_dtype, reinterpret_cast<float *>(c.ws + c.L.fac), c.s)) != FO_OK) return st;
+    if (o->preconditioner == FO_PREC_MDSC) {
+      if ((st = fo_mdsc_setup(o->mdsc, Jv, o->jac_dtype, c.s)) != FO_OK) return st;
+    } else if ((st = colblock_factor(m, Jv, o->jac_dtype, reinterpret_cast<float *>(c.ws + c.L.fac), c.s)) != FO_OK) {
+      return st;
+    }
     FO_HIP_TRY(hipStreamSynchronize(c.s));
     rep->ms_prec_construction += ms_since(t0);
     // Linear Solve: J dU = -R

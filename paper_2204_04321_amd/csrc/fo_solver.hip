@@ -151,11 +151,62 @@ __global__ __launch_bounds__(128) void colblock_factor_kernel(MeshView m, const 
   }
 }
 
-// z = M^{-1} r for every vertical line (forward then backward block substitution).  The
-// factors are stored level-major with the vertex index fastest, so a wave's loads of one
-// factor field are contiguous.  A block's columns are contiguous in r and z (2 (L+1) values
-// each): they are copied through LDS with coalesced loads and stores, and each thread runs
-// its column's two sweeps in place in LDS.
+// Forward then backward block substitution of one vertical line, in place on its 2 (L+1)
+// values zv (r in, z = M^{-1} r out).  The factors are stored level-major with the vertex index
+// fastest, so a wave's loads of one factor field are contiguous.
+__device__ __forceinline__ void column_sweep(const float *__restrict__ fac, int64_t Vl, int L, int64_t v, double *zv) {
+  // forward: y_k = r_k - Lo_k S_{k-1}^{-1} y_{k-1}; keep w_k = S_k^{-1} y_k.  The next
+  // level's factors are loaded one level ahead.
+  double f[8], fn[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) fn[i] = double(fac[int64_t(i) * Vl + v]);
+  double w0 = 0, w1 = 0;
+  for (int k = 0; k <= L; ++k) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = fn[i];
+    double y0 = zv[2 * k], y1 = zv[2 * k + 1];
+    if (k < L) {
+      const float *Fn = fac + int64_t(k + 1) * 12 * Vl + v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) fn[i] = double(Fn[i * Vl]);
+    }
+    if (k > 0) {
+      y0 -= f[4] * w0 + f[5] * w1;
+      y1 -= f[6] * w0 + f[7] * w1;
+    }
+    w0 = f[0] * y0 + f[1] * y1;
+    w1 = f[2] * y0 + f[3] * y1;
+    zv[2 * k] = w0;
+    zv[2 * k + 1] = w1;
+  }
+  // backward: z_k = w_k - G_k z_{k+1}, G_k = S_k^{-1} Up_k
+  double z0 = zv[2 * L], z1 = zv[2 * L + 1];
+  double g[4], gn[4];
+  {
+    const float *Fk = fac + int64_t(L - 1 >= 0 ? L - 1 : 0) * 12 * Vl + v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gn[i] = double(Fk[(8 + i) * Vl]);
+  }
+  for (int k = L - 1; k >= 0; --k) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[i] = gn[i];
+    if (k > 0) {
+      const float *Fn = fac + int64_t(k - 1) * 12 * Vl + v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) gn[i] = double(Fn[(8 + i) * Vl]);
+    }
+    const double n0 = zv[2 * k] - (g[0] * z0 + g[1] * z1);
+    const double n1 = zv[2 * k + 1] - (g[2] * z0 + g[3] * z1);
+    z0 = n0;
+    z1 = n1;
+    zv[2 * k] = z0;
+    zv[2 * k + 1] = z1;
+  }
+}
+
+// z = M^{-1} r for every vertical line.  A block's columns are contiguous in r and z
+// (2 (L+1) values each): they are copied through LDS with coalesced loads and stores, and
+// each thread runs its column's two sweeps in place in LDS.
 __global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V, int L, const float *__restrict__ fac,
                                                                            const double *__restrict__ r,
                                                                            double *__restrict__ z) {
@@ -165,60 +216,47 @@ __global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V
   const int nv = int(V - v0 < int64_t(blockDim.x) ? V - v0 : int64_t(blockDim.x));
   for (int e = threadIdx.x; e < nv * n; e += blockDim.x) col_sh[e] = r[v0 * n + e];
   __syncthreads();
-  if (int(threadIdx.x) < nv) {
-    const int64_t v = v0 + threadIdx.x;
-    const int64_t Vl = V;
-    double *zv = col_sh + threadIdx.x * n;   // holds r, then w, then z
-    // forward: y_k = r_k - Lo_k S_{k-1}^{-1} y_{k-1}; keep w_k = S_k^{-1} y_k.  The next
-    // level's factors are loaded one level ahead.
-    double f[8], fn[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) fn[i] = double(fac[int64_t(i) * Vl + v]);
-    double w0 = 0, w1 = 0;
-    for (int k = 0; k <= L; ++k) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) f[i] = fn[i];
-      double y0 = zv[2 * k], y1 = zv[2 * k + 1];
-      if (k < L) {
-        const float *Fn = fac + int64_t(k + 1) * 12 * Vl + v;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) fn[i] = double(Fn[i * Vl]);
-      }
-      if (k > 0) {
-        y0 -= f[4] * w0 + f[5] * w1;
-        y1 -= f[6] * w0 + f[7] * w1;
-      }
-      w0 = f[0] * y0 + f[1] * y1;
-      w1 = f[2] * y0 + f[3] * y1;
-      zv[2 * k] = w0;
-      zv[2 * k + 1] = w1;
-    }
-    // backward: z_k = w_k - G_k z_{k+1}, G_k = S_k^{-1} Up_k
-    double z0 = zv[2 * L], z1 = zv[2 * L + 1];
-    double g[4], gn[4];
-    {
-      const float *Fk = fac + int64_t(L - 1 >= 0 ? L - 1 : 0) * 12 * Vl + v;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) gn[i] = double(Fk[(8 + i) * Vl]);
-    }
-    for (int k = L - 1; k >= 0; --k) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) g[i] = gn[i];
-      if (k > 0) {
-        const float *Fn = fac + int64_t(k - 1) * 12 * Vl + v;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) gn[i] = double(Fn[(8 + i) * Vl]);
-      }
-      const double n0 = zv[2 * k] - (g[0] * z0 + g[1] * z1);
-      const double n1 = zv[2 * k + 1] - (g[2] * z0 + g[3] * z1);
-      z0 = n0;
-      z1 = n1;
-      zv[2 * k] = z0;
-      zv[2 * k + 1] = z1;
-    }
-  }
+  if (int(threadIdx.x) < nv) column_sweep(fac, V, L, v0 + threadIdx.x, col_sh + threadIdx.x * n);
   __syncthreads();
   for (int e = threadIdx.x; e < nv * n; e += blockDim.x) z[v0 * n + e] = col_sh[e];
+}
+
+// The last step of the two-level preconditioner: z = P0 y + M^{-1} (r - (J P0) y).  While the
+// block's columns are staged in LDS each row subtracts its row of J P0 (2 D values: column v's
+// rows of J P0 follow each other, 2 (L+1) rows of 2 D values, entry (r, d) at 2 r + d, the
+// block of v starting at 4 (L+1) nbr_ptr[v]) against the plane vector y; after the sweeps each
+// row adds its prolongation sum_c W[v][k][c'][c] y[(v, c)].
+__global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_correction_kernel(
+    int V, int L, const int32_t *__restrict__ nbr_ptr, const int32_t *__restrict__ nbr_idx,
+    const float *__restrict__ fac, const double *__restrict__ W, const double *__restrict__ JP,
+    const double *__restrict__ y, const double *__restrict__ r, double *__restrict__ z) {
+  extern __shared__ double col_sh[];   // [blockDim.x][2 (L + 1)]
+  const int n = 2 * (L + 1);
+  const int64_t v0 = int64_t(blockIdx.x) * blockDim.x;
+  const int nv = int(V - v0 < int64_t(blockDim.x) ? V - v0 : int64_t(blockDim.x));
+  const double2 *y2 = reinterpret_cast<const double2 *>(y);
+  for (int e = threadIdx.x; e < nv * n; e += blockDim.x) {
+    const int64_t v = v0 + e / n;
+    const int q = e - (e / n) * n;
+    const int p0 = nbr_ptr[v], D = nbr_ptr[v + 1] - p0;
+    const double *jp = JP + int64_t(2 * n) * p0 + int64_t(q) * 2 * D;
+    double s = r[v0 * n + e];
+    for (int i = 0; i < D; ++i) {
+      const double2 yw = y2[nbr_idx[p0 + i]];
+      s -= jp[2 * i] * yw.x + jp[2 * i + 1] * yw.y;
+    }
+    col_sh[e] = s;
+  }
+  __syncthreads();
+  if (int(threadIdx.x) < nv) column_sweep(fac, V, L, v0 + threadIdx.x, col_sh + threadIdx.x * n);
+  __syncthreads();
+  for (int e = threadIdx.x; e < nv * n; e += blockDim.x) {
+    const int64_t v = v0 + e / n;
+    const int q = e - (e / n) * n;
+    const double *wq = W + (v * (L + 1) + (q >> 1)) * 4 + 2 * (q & 1);
+    const double2 yv = y2[v];
+    z[v0 * n + e] = col_sh[e] + (wq[0] * yv.x + wq[1] * yv.y);
+  }
 }
 
 constexpr int RED_BLOCK = 256;
@@ -417,6 +455,19 @@ fo_status colblock_apply(const fo_mesh *mesh, const float *fac, const double *r,
   const unsigned blocks = unsigned((m.V + tpb - 1) / tpb);
   hipLaunchKernelGGL(colblock_apply_kernel, dim3(blocks), dim3(tpb), tpb * col_bytes, s, m.V, m.L, fac, r, z);
   FO_LAUNCH_CHECK("colblock_apply_kernel");
+  return FO_OK;
+}
+
+fo_status colblock_apply_correction(const fo_mesh *mesh, const float *fac, const double *W, const double *JP,
+                                    const double *y, const double *r, double *z, hipStream_t s) {
+  const MeshView &m = mesh->view;
+  const size_t col_bytes = size_t(2) * (m.L + 1) * sizeof(double);
+  int tpb = APPLY_MAX_THREADS;
+  while (tpb > 1 && tpb * col_bytes > 65536) tpb /= 2;
+  const unsigned blocks = unsigned((m.V + tpb - 1) / tpb);
+  hipLaunchKernelGGL(colblock_correction_kernel, dim3(blocks), dim3(tpb), tpb * col_bytes, s, m.V, m.L, mesh->nbr_ptr,
+                     mesh->nbr_idx, fac, W, JP, y, r, z);
+  FO_LAUNCH_CHECK("colblock_correction_kernel");
   return FO_OK;
 }
 

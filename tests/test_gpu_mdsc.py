@@ -1,0 +1,238 @@
+"""GPU two-level column semicoarsening preconditioner (fo_mdsc_*) against the oracle: the
+aggregation hierarchy bit for bit, the collapse weights, plane operators and Chebyshev bounds
+element by element, one application on random vectors, and Newton solves preconditioned by
+it against the oracle's direct-solve Newton."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from fo_inputs import config0_slab, smooth_velocity
+from fo_inputs.meshgen import ExtrudedMesh, _dome_fields, ellipse_mesh
+from oracle import fo_oracle as fo
+from oracle import mdsc, solve
+
+from gpu_util import gpu_jacobian, gpu_mesh, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _cap(n_points, L=6, seed=11, elem="wedge", sigma=None, a=70e3, b=40e3):
+    rng = np.random.default_rng(seed)
+    xy, tri = ellipse_mesh(n_points, a, b, rng)
+    s, H, beta = _dome_fields(xy, a, b, rng, 2000.0, 300.0, 500.0, 1.0, 15e3, 60e3)
+    sig = np.linspace(0, 1, L + 1) if sigma is None else sigma
+    return ExtrudedMesh(elem, xy, tri, s, H, beta, sig, A=1e-16)
+
+
+def _case(name):
+    if name == "cap400_wedge":
+        m = _cap(400)
+    elif name == "cap3000_wedge_L10":
+        m = _cap(3000, L=10, seed=5, a=250e3, b=120e3)
+    elif name == "slab_hex":
+        m, U = config0_slab()
+        return m, U
+    elif name == "cap400_tet":
+        m = _cap(400, L=4, elem="tet")
+    elif name == "tiny_exact_plane":
+        m = _cap(50, L=3, seed=2)
+    elif name == "single_layer":
+        m = _cap(600, L=1, seed=3)
+    elif name == "graded_sigma":
+        m = _cap(500, L=8, seed=4, sigma=np.linspace(0, 1, 9) ** 1.7)
+    else:
+        raise KeyError(name)
+    return m, solve.sia_guess(m) + smooth_velocity(m, np.random.default_rng(1), u_scale=5.0)
+
+
+CASES = ["cap400_wedge", "cap3000_wedge_L10", "slab_hex", "cap400_tet", "tiny_exact_plane", "single_layer",
+         "graded_sigma"]
+
+
+def _oracle_levels(m):
+    """Graphs and aggregates of every plane level, by the oracle's rules."""
+    nbrs = mdsc.plane_graph(m)
+    out = []
+    while True:
+        if len(nbrs) <= mdsc.COARSEST_MAX:
+            out.append((nbrs, None))
+            return out
+        agg, n_agg = mdsc.aggregate(nbrs)
+        out.append((nbrs, agg))
+        nbrs = mdsc.coarse_graph(nbrs, agg, n_agg)
+
+
+def _blocks_of(A, ptr, idx):
+    """The 2x2 blocks of a scalar plane matrix at a block pattern: [nnzb, 4]."""
+    A = sp.csr_matrix(A)
+    rows = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))
+    out = np.empty((len(idx), 4))
+    for c in range(2):
+        for d in range(2):
+            out[:, 2 * c + d] = np.asarray(A[2 * rows + c, 2 * idx + d]).ravel()
+    return out
+
+
+@pytest.fixture(scope="module", params=CASES)
+def setup_case(request):
+    from paper_2204_04321_amd.api import Mdsc
+    name = request.param
+    m, U = _case(name)
+    print(f"\n[mdsc] case {name}: V {m.n_verts} L {m.n_layers} elem {m.elem}", flush=True)
+    M = gpu_mesh(m)
+    P = Mdsc(M)
+    _, Jg = gpu_jacobian(M, U)
+    _, Jvals = M.jacobian(to_dev(U))
+    P.setup(Jvals)
+    torch.cuda.synchronize()
+    _, Jo = fo.assemble(m, U)
+    H = mdsc.Hierarchy(m, Jo.tocsr())
+    return name, m, U, M, P, H, Jvals
+
+
+def test_hierarchy_graphs_and_aggregates(setup_case):
+    name, m, U, M, P, H, _ = setup_case
+    want = _oracle_levels(m)
+    assert P.n_levels == len(want) - 1 == len(H.levels), name
+    for lvl, (nbrs, agg) in enumerate(want):
+        ptr, idx, gagg = P.graph(lvl)
+        assert np.array_equal(np.diff(ptr), [len(l) for l in nbrs]), (name, lvl)
+        assert np.array_equal(idx, np.concatenate(nbrs)), (name, lvl)
+        if agg is None:
+            assert gagg is None
+        else:
+            assert np.array_equal(gagg, agg), (name, lvl)
+
+
+def test_weights_plane_operators_and_bounds(setup_case):
+    """FP64 setup against the oracle: the weights within 1e-11 of each weight vector's largest
+    entry (a recursion against a dense solve of the same column, both backward stable: the
+    difference is bounded by the column block's condition number times rounding, and the
+    bar leaves room for condition numbers up to ~1e4), the plane blocks within 1e-10 of each
+    level's largest block entry (sums of those weights times Jacobian values), the Gershgorin
+    bounds within 1e-10 relative."""
+    name, m, U, M, P, H, _ = setup_case
+    W = P.export("weights").reshape(H.W.shape)
+    scale = np.abs(H.W).max(axis=(1, 2))[:, None, None, :]
+    err_w = (np.abs(W - H.W) / scale).max()
+    errs = [err_w]
+    for lvl in range(P.n_levels + 1):
+        ptr, idx, _ = P.graph(lvl)
+        A_g = P.export("plane", lvl).reshape(-1, 4)
+        A_o = _blocks_of(H.levels[lvl]["A"] if lvl < len(H.levels) else H.A_coarse, ptr, idx)
+        e = np.abs(A_g - A_o).max() / np.abs(A_o).max()
+        errs.append(e)
+        assert e <= 1e-10, (name, lvl, e)
+        if lvl < P.n_levels:
+            g = P.export("bound", lvl)[0]
+            assert abs(g - H.levels[lvl]["g"]) <= 1e-10 * H.levels[lvl]["g"], (name, lvl)
+    print(f"[mdsc] {name}: weights {err_w:.1e}, plane levels " + " ".join(f"{e:.1e}" for e in errs[1:]))
+    assert err_w <= 1e-11, (name, err_w)
+
+
+def test_apply_matches_oracle(setup_case):
+    """z = M^-1 r for random r against the oracle's application of the same hierarchy.  Both
+    store the column factors in FP32 from FP64 recursions that agree to rounding, so a factor
+    can round to neighbouring FP32 values on the two sides (a relative change of 6e-8 in one
+    factor); the bar 1e-6 of max |z| allows that change times the column solve's
+    amplification.  Two vectors, the second after a second setup of the same Jacobian (the
+    numeric state is rebuilt, not accumulated)."""
+    name, m, U, M, P, H, Jvals = setup_case
+    rng = np.random.default_rng(3)
+    for rep in range(2):
+        if rep == 1:
+            P.setup(Jvals)
+        r = rng.normal(size=m.n_dofs)
+        z = P.apply(to_dev(r)).cpu().numpy()
+        want = H.apply(r)
+        err = np.abs(z - want).max() / np.abs(want).max()
+        print(f"[mdsc] {name}: apply {err:.1e}")
+        assert err <= 1e-6, (name, err)
+
+
+@pytest.fixture(scope="module")
+def cap_solution():
+    m = _cap(400)
+    U_ref, info = solve.newton_solve(m, solve.sia_guess(m), tol=1e-11)
+    assert info["status"] == "converged"
+    return m, U_ref, gpu_mesh(m)
+
+
+@pytest.mark.parametrize("jdt", ["f64", "f32"])
+def test_newton_with_mdsc_matches_oracle_solution(cap_solution, jdt):
+    from paper_2204_04321_amd.api import Mdsc
+    m, U_ref, M = cap_solution
+    P = Mdsc(M)
+    U = to_dev(solve.sia_guess(m))
+    rep = M.newton_solve(U, tol=1e-8, jac_dtype=jdt, preconditioner="mdsc", mdsc=P)
+    U0 = to_dev(solve.sia_guess(m))
+    base = M.newton_solve(U0, tol=1e-8, jac_dtype=jdt)
+    print(f"\n[newton mdsc {jdt}] its {rep['newton_its']} gmres {rep['lin_its']} (column: {base['newton_its']} / "
+          f"{base['lin_its']}) res {rep['final_rel']:.2e}")
+    assert rep["status"] == 0, rep
+    Ug = U.cpu().numpy()
+    f0 = np.linalg.norm(fo.residual(m, np.zeros_like(Ug)))
+    assert np.linalg.norm(fo.residual(m, Ug)) <= 1.01e-8 * f0
+    diff = np.abs(Ug - U_ref).max() / np.abs(U_ref).max()
+    assert diff <= 1e-6, diff
+    assert rep["lin_its"] < base["lin_its"], (rep["lin_its"], base["lin_its"])
+
+
+def _icesheet_patch(n_points, seed=1):
+    """The ice-sheet configuration (dome, bed and log-normal beta fields, 10 layers) on an
+    ellipse scaled down with the point count, so the base spacing stays the ice sheet's."""
+    rng = np.random.default_rng(seed)
+    sc = (n_points / 125_000) ** 0.5
+    a, b = 750e3 * sc, 350e3 * sc
+    xy, tri = ellipse_mesh(n_points, a, b, rng)
+    s, H, beta = _dome_fields(xy, a, b, rng, 3000.0, 500.0, 500.0, 1.0, 30e3 * sc, 200e3 * sc)
+    return ExtrudedMesh("wedge", xy, tri, s, H, beta, np.linspace(0, 1, 11), A=1e-16)
+
+
+def test_mdsc_cuts_gmres_iterations_on_an_icesheet_patch():
+    """6000 base points at the ice sheet's spacing, 10 layers: fewer GMRES iterations per
+    Newton step than the column preconditioner."""
+    from paper_2204_04321_amd.api import Mdsc
+    m = _icesheet_patch(6000)
+    M = gpu_mesh(m)
+    P = Mdsc(M)
+    out = {}
+    for prec in ("column", "mdsc"):
+        U = to_dev(solve.sia_guess(m))
+        kw = {"preconditioner": "mdsc", "mdsc": P} if prec == "mdsc" else {}
+        rep = M.newton_solve(U, tol=1e-8, **kw)
+        assert rep["status"] == 0, (prec, rep)
+        out[prec] = rep
+        print(f"\n[newton patch6000 {prec}] its {rep['newton_its']} gmres {rep['lin_its']} "
+              f"({rep['lin_its'] / max(rep['newton_its'], 1):.1f} per step) lin {rep['ms_linear_solve']:.1f} ms")
+    per = {k: v["lin_its"] / max(v["newton_its"], 1) for k, v in out.items()}
+    assert per["mdsc"] < 0.8 * per["column"], per
+
+
+def test_mdsc_argument_errors():
+    from paper_2204_04321_amd.api import Mdsc
+    from paper_2204_04321_amd._lib import FoError
+    m = _cap(120, L=2, seed=8)
+    M, M2 = gpu_mesh(m), gpu_mesh(m)
+    P = Mdsc(M)
+    U = to_dev(solve.sia_guess(m))
+    with pytest.raises(FoError, match="no successful fo_mdsc_setup"):
+        P.apply(torch.zeros_like(U))
+    rep = M2.newton_solve(U.clone(), preconditioner="mdsc", mdsc=P)
+    assert rep["status"] == -1 and "created on this mesh" in rep["message"]
+    rep = M.newton_solve(U.clone(), preconditioner="mdsc", mdsc=P, linear_solver="pcg")
+    assert rep["status"] == -1 and "not symmetric" in rep["message"]
+    rep = M.newton_solve(U.clone(), preconditioner="mdsc", mdsc=None)
+    assert rep["status"] == -1
+    # a non-finite Jacobian value makes a plane diagonal block non-finite: reported, no apply
+    _, J = M.jacobian(U)
+    J[0] = float("nan")
+    with pytest.raises(FoError, match="singular or not finite"):
+        P.setup(J)
+    with pytest.raises(FoError, match="no successful fo_mdsc_setup"):
+        P.apply(torch.zeros_like(U))
+    r = torch.zeros_like(U)
+    with pytest.raises(FoError, match="aliased"):
+        from paper_2204_04321_amd import _lib
+        _lib.check(_lib.lib().fo_mdsc_apply(P.handle, r.data_ptr(), r.data_ptr(), None))
