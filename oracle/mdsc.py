@@ -10,7 +10,10 @@ writes out the preconditioner the library implements in that spirit, step by ste
 
   * column smoother B: block LU without pivoting of each vertex column's block-tridiagonal
     matrix (2x2 blocks per level, FP64 recursion), the stored factors rounded to FP32, the
-    substitutions in FP64 (the column block preconditioner of the plain GMRES path);
+    substitutions in FP64 (the column block preconditioner of the plain GMRES path); J P0 and
+    the weights that restrict and prolong are stored in FP32 as well (any stored precision
+    leaves the preconditioner a fixed linear operator, which is all right preconditioning
+    needs), the plane operators are formed in FP64;
   * vertical collapse P0 (one step to a single layer): per column v and component c the
     weight vector w = B_v^{-1} e_c, e_c holding 1 at component c of every level, scaled so
     that the mean of its component-c entries is 1 (reading: the vertical profile the
@@ -28,9 +31,11 @@ writes out the preconditioner the library implements in that spirit, step by ste
     unsmoothed (piecewise-constant, both components per vertex) transfers T and Galerkin
     operators T^T A T (reading: plain aggregation in place of smoothed aggregation; the
     smoothed form gave the same GMRES counts on the ice-sheet meshes);
-  * smoother on each plane level: Chebyshev of degree 2 on D^{-1} A (D the 2x2 diagonal
-    blocks) over [g / 30, g], g the Gershgorin bound max_i sum_j |(D^{-1} A)_ij| (reading:
-    the paper names Chebyshev; the bound replaces a power-iteration estimate);
+  * smoother on each plane level: Chebyshev on D^{-1} A (D the 2x2 diagonal blocks) over
+    [g / 30, g], g the Gershgorin bound max_i sum_j |(D^{-1} A)_ij| (reading: the paper names
+    Chebyshev; the bound replaces a power-iteration estimate), of degree 2 on the first plane
+    level and degree 1 (one damped Jacobi step) on the coarser ones, which gave the same GMRES
+    counts on the ice-sheet meshes as degree 2 everywhere;
   * V-cycle: pre-smooth from zero, restrict the residual, recurse, prolong, post-smooth; the
     coarsest level solved exactly;
   * one application: y = V-cycle(P0^T r), z = P0 y + B (r - J P0 y) (coarse correction first,
@@ -45,7 +50,7 @@ import scipy.sparse as sp
 
 COARSEST_MAX = 64          # plane vertices solved exactly
 ISOLATED_GROUP = 8         # isolated vertices per aggregate
-CHEB_DEGREE = 2
+CHEB_DEGREES = (2, 1)     # first plane level, coarser levels
 CHEB_RATIO = 30.0
 
 
@@ -222,7 +227,7 @@ def gershgorin(A, Dinv) -> float:
     return float(np.asarray(M.sum(axis=1)).max())
 
 
-def chebyshev(A, Dinv, g, b, x, degree=CHEB_DEGREE, ratio=CHEB_RATIO):
+def chebyshev(A, Dinv, g, b, x, degree, ratio=CHEB_RATIO):
     """`degree` Chebyshev steps for A x = b preconditioned by D, over [g / ratio, g]
     (three-term recurrence: theta and delta the centre and half-width of the interval,
     sigma = theta / delta, rho_0 = 1 / sigma, d_0 = D^{-1} r_0 / theta,
@@ -242,17 +247,23 @@ def chebyshev(A, Dinv, g, b, x, degree=CHEB_DEGREE, ratio=CHEB_RATIO):
 
 
 class Hierarchy:
-    """The preconditioner of one Jacobian J (FP64 values) on one mesh."""
+    """The preconditioner of one Jacobian J (FP64 values) on one mesh.  The parts that every
+    application reads (column factors, J P0 and the weights of the restriction and
+    prolongation) are stored rounded to `store` (FP32, as the library stores them; FP64 for
+    the exactness pins); the plane operators are formed from the FP64 values."""
 
-    def __init__(self, mesh, J):
+    def __init__(self, mesh, J, store=np.float32):
         J = sp.csr_matrix(J)
         self.J = J
+        rnd = lambda a: a.astype(store).astype(np.float64)
         blocks = column_blocks(mesh, J)
-        self.factors = column_factors(blocks)
+        self.factors = column_factors(blocks, store=store)
         self.W = vertical_weights(blocks)
         self.P0 = collapse(mesh, self.W)
-        self.JP = (J @ self.P0).tocsr()
-        A = (self.P0.T @ self.JP).tocsr()
+        JP = (J @ self.P0).tocsr()
+        A = (self.P0.T @ JP).tocsr()
+        self.JP = sp.csr_matrix((rnd(JP.data), JP.indices, JP.indptr), shape=JP.shape)
+        self.P0s = collapse(mesh, rnd(self.W))
         nbrs = plane_graph(mesh)
         self.levels = []     # dicts: A, Dinv, g, agg, n_agg, T
         while len(nbrs) > COARSEST_MAX:
@@ -269,11 +280,12 @@ class Hierarchy:
             return np.linalg.solve(self.A_coarse, b)
         lv = self.levels[level]
         A, Dinv, g, T = lv["A"], lv["Dinv"], lv["g"], lv["T"]
-        x = chebyshev(A, Dinv, g, b, np.zeros_like(b))
+        deg = CHEB_DEGREES[0] if level == 0 else CHEB_DEGREES[1]
+        x = chebyshev(A, Dinv, g, b, np.zeros_like(b), deg)
         x = x + T @ self.vcycle(T.T @ (b - A @ x), level + 1)
-        return chebyshev(A, Dinv, g, b, x)
+        return chebyshev(A, Dinv, g, b, x, deg)
 
     def apply(self, r):
         r = np.asarray(r, dtype=np.float64)
-        y = self.vcycle(self.P0.T @ r)
-        return self.P0 @ y + column_solve(self.factors, r - self.JP @ y)
+        y = self.vcycle(self.P0s.T @ r)
+        return self.P0s @ y + column_solve(self.factors, r - self.JP @ y)

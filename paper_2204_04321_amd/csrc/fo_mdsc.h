@@ -38,7 +38,16 @@ struct PlaneLevel {
   int32_t *agg = nullptr;       // [n] aggregate of each vertex (smoothed levels)
   int32_t *mptr = nullptr, *midx = nullptr;   // members of the next level's vertices
   int32_t *gptr = nullptr, *gidx = nullptr;   // Galerkin gather lists for the next level
-  double *b = nullptr, *x = nullptr, *x2 = nullptr, *d = nullptr, *r = nullptr;   // [2 n]
+  double *b = nullptr, *x = nullptr;          // [2 n] right-hand side and iterate
+  double *x2 = nullptr, *d = nullptr;         // [2 n] degree-2 smoothing state (first level only)
+};
+
+// The device view of one plane level (what the V-cycle kernels read).
+struct LevelDev {
+  int32_t n;
+  const int32_t *ptr, *idx, *agg, *mptr, *midx;
+  const double *A, *Dinv, *g;
+  double *b, *x, *x2, *d;
 };
 
 }  // namespace fo
@@ -48,11 +57,14 @@ struct fo_mdsc {
   int device = 0;
   std::vector<fo::PlaneLevel> lv;   // lv.back() is the coarsest
   int32_t *blk_row = nullptr;       // [nnzb of level 0] row vertex of each block
+  fo::LevelDev *lv_dev = nullptr;   // [levels] device copies of the level views
   float *fac = nullptr;             // column factors, the layout of the column preconditioner
-  double *W = nullptr;              // [V][L+1][2][2] collapse weights
-  double *JP = nullptr;             // J P0: per column v, 2 (L+1) rows of 2 D_v values
+  double *W = nullptr;              // [V][L+1][2][2] collapse weights (FP64, for the setup)
+  float *W32 = nullptr;             // the same rounded to FP32 (restriction and prolongation)
+  float *JP = nullptr;              // J P0 (FP32) by plane block e = (v, r): entry d of row q
+                                    // of column v at (2 e + d) 2 (L+1) + q
   size_t jp_count = 0;
-  double *Ainv = nullptr;           // coarsest inverse, column-major [nc][nc]
+  double *Ainv = nullptr;           // coarsest inverse, row-major [nc][nc]
   int32_t *flag = nullptr;          // device status of the last setup
   int32_t *flag_host = nullptr;     // pinned
   bool ready = false;

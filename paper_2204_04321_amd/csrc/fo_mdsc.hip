@@ -8,9 +8,10 @@
 // one pass over J that forms J P0 and the plane operator P0^T J P0 block by block, the plane
 // levels' diagonal inverses and Gershgorin bounds, Galerkin sums through precomputed gather
 // lists (fixed order, no atomics) and the coarsest inverse in one workgroup's LDS.
-// Application: restrict with W, a V-cycle over the plane levels (Chebyshev degree 2 before
-// and after each coarse correction, each fused into one kernel with the residual it needs),
-// then the column smoother on r - J P0 y fused with the prolongation P0 y.
+// Application: restrict with W, a V-cycle over the plane levels (Chebyshev before and after
+// each coarse correction, degree 2 on the first plane level and 1 below it, each step one
+// kernel that forms the residual it needs), then the column smoother on r - J P0 y fused with
+// the prolongation P0 y.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,111 +41,132 @@ __device__ __forceinline__ void mul22(const double *a, const double *b, double *
 }
 
 // Collapse weights of one vertex column per thread.  Forward: S_k = D_k - Lo_k G_{k-1},
-// G_k = S_k^-1 Up_k (kept in Gs), Y_k = S_k^-1 (I - Lo_k Y_{k-1}) for the two right-hand sides
-// e_u, e_v at once (Y_k is 2x2: rows the level's components, columns the right-hand sides);
-// backward Z_k = Y_k - G_k Z_{k+1}; then each right-hand side's solution is divided by the
-// mean of its own component over the levels (e_c itself where that is not usable).
+// G_k = S_k^-1 Up_k, Y_k = S_k^-1 (I - Lo_k Y_{k-1}) for the two right-hand sides e_u, e_v at
+// once (Y_k is 2x2: rows the level's components, columns the right-hand sides); backward
+// Z_k = Y_k - G_k Z_{k+1}; then each right-hand side's solution is divided by the mean of its
+// own component over the levels (e_c itself where that is not usable).  The block's columns
+// (4 (L+1) values each, G and Y/Z) live in LDS and leave with coalesced stores, in FP64 and
+// rounded to FP32.
 template <class JT>
-__global__ __launch_bounds__(128) void weights_kernel(MeshView m, const int32_t *__restrict__ self_rank,
-                                                      const JT *__restrict__ J, double *__restrict__ W,
-                                                      double *__restrict__ Gs) {
-  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= m.V) return;
-  const int L = m.L, D = m.deg[v], sr = self_rank[v];
-  const int64_t base = m.colptr[v];
-  double *Wv = W + int64_t(v) * (L + 1) * 4;
-  double *Gv = Gs + int64_t(v) * (L + 1) * 4;
-  double Gp[4] = {0, 0, 0, 0}, Yp[4] = {0, 0, 0, 0};
-  for (int k = 0; k <= L; ++k) {
-    const int nl = nlev(k, L), kmin = k > 0 ? k - 1 : 0;
-    double Dk[4], Lo[4] = {0, 0, 0, 0}, Up[4] = {0, 0, 0, 0};
-    for (int c = 0; c < 2; ++c) {
-      const int64_t row = base + int64_t(4) * D * cumlev(k) + int64_t(c) * 2 * nl * D + int64_t(sr) * 2 * nl;
-      for (int d = 0; d < 2; ++d) {
-        Dk[2 * c + d] = double(J[row + 2 * (k - kmin) + d]);
-        if (k > 0) Lo[2 * c + d] = double(J[row + 2 * (k - 1 - kmin) + d]);
-        if (k < L) Up[2 * c + d] = double(J[row + 2 * (k + 1 - kmin) + d]);
+__global__ __launch_bounds__(64) void weights_kernel(MeshView m, const int32_t *__restrict__ self_rank,
+                                                     const JT *__restrict__ J, double *__restrict__ W,
+                                                     float *__restrict__ W32) {
+  extern __shared__ double wsh[];   // [2][blockDim.x][4 (L + 1)]: Z then G
+  const int L = m.L, nw = 4 * (L + 1);
+  const int64_t v0 = int64_t(blockIdx.x) * blockDim.x;
+  const int nv = int(m.V - v0 < int64_t(blockDim.x) ? m.V - v0 : int64_t(blockDim.x));
+  if (int(threadIdx.x) < nv) {
+    const int64_t v = v0 + threadIdx.x;
+    const int D = m.deg[v], sr = self_rank[v];
+    const int64_t base = m.colptr[v];
+    double *Wv = wsh + threadIdx.x * nw;
+    double *Gv = wsh + (blockDim.x + threadIdx.x) * nw;
+    double Gp[4] = {0, 0, 0, 0}, Yp[4] = {0, 0, 0, 0};
+    for (int k = 0; k <= L; ++k) {
+      const int nl = nlev(k, L), kmin = k > 0 ? k - 1 : 0;
+      double Dk[4], Lo[4] = {0, 0, 0, 0}, Up[4] = {0, 0, 0, 0};
+      for (int c = 0; c < 2; ++c) {
+        const int64_t row = base + int64_t(4) * D * cumlev(k) + int64_t(c) * 2 * nl * D + int64_t(sr) * 2 * nl;
+        for (int d = 0; d < 2; ++d) {
+          Dk[2 * c + d] = double(J[row + 2 * (k - kmin) + d]);
+          if (k > 0) Lo[2 * c + d] = double(J[row + 2 * (k - 1 - kmin) + d]);
+          if (k < L) Up[2 * c + d] = double(J[row + 2 * (k + 1 - kmin) + d]);
+        }
+      }
+      double T[4] = {1, 0, 0, 1};
+      if (k > 0) {
+        double t[4];
+        mul22(Lo, Gp, t);
+        for (int i = 0; i < 4; ++i) Dk[i] -= t[i];
+        mul22(Lo, Yp, t);
+        for (int i = 0; i < 4; ++i) T[i] -= t[i];
+      }
+      const double det = Dk[0] * Dk[3] - Dk[1] * Dk[2];
+      const double Si[4] = {Dk[3] / det, -Dk[1] / det, -Dk[2] / det, Dk[0] / det};
+      mul22(Si, Up, Gp);
+      mul22(Si, T, Yp);
+      for (int i = 0; i < 4; ++i) {
+        Gv[4 * k + i] = Gp[i];
+        Wv[4 * k + i] = Yp[i];
       }
     }
-    double T[4] = {1, 0, 0, 1};
-    if (k > 0) {
+    double Z[4] = {Wv[4 * L], Wv[4 * L + 1], Wv[4 * L + 2], Wv[4 * L + 3]};
+    for (int k = L - 1; k >= 0; --k) {
+      const double G[4] = {Gv[4 * k], Gv[4 * k + 1], Gv[4 * k + 2], Gv[4 * k + 3]};
       double t[4];
-      mul22(Lo, Gp, t);
-      for (int i = 0; i < 4; ++i) Dk[i] -= t[i];
-      mul22(Lo, Yp, t);
-      for (int i = 0; i < 4; ++i) T[i] -= t[i];
+      mul22(G, Z, t);
+      for (int i = 0; i < 4; ++i) {
+        Z[i] = Wv[4 * k + i] - t[i];
+        Wv[4 * k + i] = Z[i];
+      }
     }
-    const double det = Dk[0] * Dk[3] - Dk[1] * Dk[2];
-    const double Si[4] = {Dk[3] / det, -Dk[1] / det, -Dk[2] / det, Dk[0] / det};
-    mul22(Si, Up, Gp);
-    mul22(Si, T, Yp);
-    for (int i = 0; i < 4; ++i) {
-      Gv[4 * k + i] = Gp[i];
-      Wv[4 * k + i] = Yp[i];
-    }
-  }
-  double Z[4] = {Wv[4 * L], Wv[4 * L + 1], Wv[4 * L + 2], Wv[4 * L + 3]};
-  for (int k = L - 1; k >= 0; --k) {
-    const double G[4] = {Gv[4 * k], Gv[4 * k + 1], Gv[4 * k + 2], Gv[4 * k + 3]};
-    double t[4];
-    mul22(G, Z, t);
-    for (int i = 0; i < 4; ++i) {
-      Z[i] = Wv[4 * k + i] - t[i];
-      Wv[4 * k + i] = Z[i];
+    for (int c = 0; c < 2; ++c) {
+      double sum = 0.0;
+      bool finite = true;
+      for (int k = 0; k <= L; ++k) {
+        sum += Wv[4 * k + 2 * c + c];
+        finite = finite && isfinite(Wv[4 * k + c]) && isfinite(Wv[4 * k + 2 + c]);
+      }
+      const double mean = sum / double(L + 1);
+      const bool ok = finite && isfinite(mean) && mean > 0.0;
+      for (int k = 0; k <= L; ++k)
+        for (int cp = 0; cp < 2; ++cp)
+          Wv[4 * k + 2 * cp + c] = ok ? Wv[4 * k + 2 * cp + c] / mean : (cp == c ? 1.0 : 0.0);
     }
   }
-  for (int c = 0; c < 2; ++c) {
-    double sum = 0.0;
-    bool finite = true;
-    for (int k = 0; k <= L; ++k) {
-      sum += Wv[4 * k + 2 * c + c];
-      finite = finite && isfinite(Wv[4 * k + c]) && isfinite(Wv[4 * k + 2 + c]);
-    }
-    const double mean = sum / double(L + 1);
-    const bool ok = finite && isfinite(mean) && mean > 0.0;
-    for (int k = 0; k <= L; ++k)
-      for (int cp = 0; cp < 2; ++cp)
-        Wv[4 * k + 2 * cp + c] = ok ? Wv[4 * k + 2 * cp + c] / mean : (cp == c ? 1.0 : 0.0);
+  __syncthreads();
+  for (int e = threadIdx.x; e < nv * nw; e += blockDim.x) {
+    const double w = wsh[e];
+    W[v0 * nw + e] = w;
+    W32[v0 * nw + e] = float(w);
   }
 }
 
-// One thread per plane block (v, neighbour r = w): the rows of J P0 of column v against
-// column w, T[(k, c')][d] = sum over the levels l of J_{(v,k,c'),(w,l,d')} W_w[l][d'][d],
-// stored as J P0 (column v: 2 (L+1) rows of 2 D values, entry (r, d) at 2 r + d), and the
-// block A_0[v][w][c][d] = sum_k sum_c' W_v[k][c'][c] T[(k, c')][d].
+// One thread per plane block e = (v, neighbour r = w): the rows of J P0 of column v against
+// column w, T[(k, c')][d] = sum over the levels l of J_{(v,k,c'),(w,l,d')} W_w[l][d'][d], and
+// the block A_0[v][w][c][d] = sum_k sum_c' W_v[k][c'][c] T[(k, c')][d] from the FP64 values.
+// J P0 is stored in FP32 by block: entry d of row q of block e at (2 e + d) 2 (L+1) + q (for a
+// column, entry (r, d) of row q at (2 (nbr_ptr[v] + r) + d) 2 (L+1) + q), so a workgroup's
+// blocks own one contiguous range, staged in LDS and written with coalesced stores.
 template <class JT>
 __global__ __launch_bounds__(256) void plane_kernel(MeshView m, const int32_t *__restrict__ nbr_ptr,
                                                     const int32_t *__restrict__ nbr_idx,
                                                     const int32_t *__restrict__ blk_row, int32_t nnzb,
                                                     const JT *__restrict__ J, const double *__restrict__ W,
-                                                    double *__restrict__ JP, double *__restrict__ A0) {
-  const int e = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= nnzb) return;
-  const int v = blk_row[e], nb0 = nbr_ptr[v], r = e - nb0, D = nbr_ptr[v + 1] - nb0, w = nbr_idx[e];
+                                                    float *__restrict__ JP, double *__restrict__ A0) {
+  extern __shared__ float jsh[];   // [blockDim.x][2][2 (L + 1)]
   const int L = m.L, nb = 2 * (L + 1);
-  const int64_t base = m.colptr[v];
-  const double *Wv = W + int64_t(v) * (L + 1) * 4, *Ww = W + int64_t(w) * (L + 1) * 4;
-  double *JPv = JP + int64_t(nb) * 2 * nb0;
-  double a[4] = {0, 0, 0, 0};
-  for (int k = 0; k <= L; ++k) {
-    const int nl = nlev(k, L), klo = k > 0 ? k - 1 : 0;
-    double T[4] = {0, 0, 0, 0};
-    for (int cp = 0; cp < 2; ++cp) {
-      const int64_t row = base + int64_t(4) * D * cumlev(k) + int64_t(cp) * 2 * nl * D + int64_t(r) * 2 * nl;
-      for (int lev = 0; lev < nl; ++lev) {
-        const double j0 = double(J[row + 2 * lev]), j1 = double(J[row + 2 * lev + 1]);
-        const double *wl = Ww + 4 * (klo + lev);
-        T[2 * cp] += j0 * wl[0] + j1 * wl[2];
-        T[2 * cp + 1] += j0 * wl[1] + j1 * wl[3];
+  const int e0 = int(blockIdx.x) * blockDim.x, e = e0 + threadIdx.x;
+  const int ne = nnzb - e0 < int(blockDim.x) ? nnzb - e0 : int(blockDim.x);
+  if (e < nnzb) {
+    const int v = blk_row[e], nb0 = nbr_ptr[v], r = e - nb0, D = nbr_ptr[v + 1] - nb0, w = nbr_idx[e];
+    const int64_t base = m.colptr[v];
+    const double *Wv = W + int64_t(v) * (L + 1) * 4, *Ww = W + int64_t(w) * (L + 1) * 4;
+    float *J0 = jsh + threadIdx.x * 2 * nb, *J1 = J0 + nb;
+    double a[4] = {0, 0, 0, 0};
+    for (int k = 0; k <= L; ++k) {
+      const int nl = nlev(k, L), klo = k > 0 ? k - 1 : 0;
+      double T[4] = {0, 0, 0, 0};
+      for (int cp = 0; cp < 2; ++cp) {
+        const int64_t row = base + int64_t(4) * D * cumlev(k) + int64_t(cp) * 2 * nl * D + int64_t(r) * 2 * nl;
+        for (int lev = 0; lev < nl; ++lev) {
+          const double j0 = double(J[row + 2 * lev]), j1 = double(J[row + 2 * lev + 1]);
+          const double *wl = Ww + 4 * (klo + lev);
+          T[2 * cp] += j0 * wl[0] + j1 * wl[2];
+          T[2 * cp + 1] += j0 * wl[1] + j1 * wl[3];
+        }
+        J0[2 * k + cp] = float(T[2 * cp]);
+        J1[2 * k + cp] = float(T[2 * cp + 1]);
       }
-      JPv[int64_t(2 * k + cp) * 2 * D + 2 * r] = T[2 * cp];
-      JPv[int64_t(2 * k + cp) * 2 * D + 2 * r + 1] = T[2 * cp + 1];
+      const double *wv = Wv + 4 * k;
+      for (int c = 0; c < 2; ++c)
+        for (int d = 0; d < 2; ++d) a[2 * c + d] += wv[c] * T[d] + wv[2 + c] * T[2 + d];
     }
-    const double *wv = Wv + 4 * k;
-    for (int c = 0; c < 2; ++c)
-      for (int d = 0; d < 2; ++d) a[2 * c + d] += wv[c] * T[d] + wv[2 + c] * T[2 + d];
+    for (int i = 0; i < 4; ++i) A0[4 * int64_t(e) + i] = a[i];
   }
-  for (int i = 0; i < 4; ++i) A0[4 * int64_t(e) + i] = a[i];
+  __syncthreads();
+  float *out = JP + int64_t(2) * nb * e0;
+  for (int t = threadIdx.x; t < ne * 2 * nb; t += blockDim.x) out[t] = jsh[t];
 }
 
 // Diagonal-block inverse of every plane vertex and its Gershgorin row bound
@@ -274,9 +296,10 @@ __global__ __launch_bounds__(256) void coarse_inverse_kernel(int n, const int32_
     for (int j = tid; j < nc; j += bd) a[k * nc + j] = (j == k ? 1.0 : a[k * nc + j]) / piv;
     for (int i = tid; i < nc; i += bd) fcol[i] = i == k ? 0.0 : a[i * nc + k];
     __syncthreads();
-    for (int t = tid; t < nc * nc; t += bd) {
-      const int i = t / nc, j = t - (t / nc) * nc;
-      if (i != k) a[t] = (j == k ? 0.0 : a[t]) - fcol[i] * a[k * nc + j];
+    for (int i = tid >> 4; i < nc; i += bd >> 4) {   // 16 threads per row group, no divisions
+      if (i == k) continue;
+      const double f = fcol[i];
+      for (int j = tid & 15; j < nc; j += 16) a[i * nc + j] = (j == k ? 0.0 : a[i * nc + j]) - f * a[k * nc + j];
     }
     __syncthreads();
   }
@@ -294,10 +317,7 @@ __global__ __launch_bounds__(256) void coarse_inverse_kernel(int n, const int32_
       }
     __syncthreads();
   }
-  for (int t = tid; t < nc * nc; t += bd) {
-    const int i = t / nc, j = t - (t / nc) * nc;
-    Ainv[int64_t(j) * nc + i] = a[t];
-  }
+  for (int t = tid; t < nc * nc; t += bd) Ainv[t] = a[t];
 }
 
 // ---- application ------------------------------------------------------------------------
@@ -319,135 +339,188 @@ __device__ __forceinline__ double2 apply22(const double *Dv, double2 x) {
   return make_double2(Dv[0] * x.x + Dv[1] * x.y, Dv[2] * x.x + Dv[3] * x.y);
 }
 
-// b_0[(v, c)] = sum over the column's levels and components of W[v][k][c'][c] r[(v, k, c')]
-__global__ __launch_bounds__(256) void restrict_fine_kernel(int V, int L, const double *__restrict__ W,
+// b_0[(v, c)] = sum over the column's levels and components of W[v][k][c'][c] r[(v, k, c')].
+// The products of a block of columns are staged in LDS (coalesced loads of r and of the FP32
+// weights, whose two columns c sit next to each other for every row), then one thread per
+// (column, c) sums its column's rows in level order.
+__global__ __launch_bounds__(128) void restrict_fine_kernel(int V, int L, int cols, const float *__restrict__ W32,
                                                             const double *__restrict__ r, double *__restrict__ b0) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= 2 * int64_t(V)) return;
-  const int64_t v = t >> 1;
-  const int c = int(t & 1);
-  const double *Wv = W + v * (L + 1) * 4;
-  const double *rv = r + v * 2 * (L + 1);
-  double s = 0.0;
-  for (int k = 0; k <= L; ++k) s += Wv[4 * k + c] * rv[2 * k] + Wv[4 * k + 2 + c] * rv[2 * k + 1];
-  b0[t] = s;
-}
-
-// Pre-smoothing from x = 0: x1 = D^-1 b / theta, x = x1 + c1 x1 + c2 D^-1 (b - A x1), with x1
-// of the neighbours formed on the fly.
-__global__ __launch_bounds__(256) void cheb_pre_kernel(int n, const int32_t *__restrict__ ptr,
-                                                       const int32_t *__restrict__ idx, const double *__restrict__ A,
-                                                       const double *__restrict__ Dinv, const double *__restrict__ g,
-                                                       const double *__restrict__ b, double *__restrict__ x) {
-  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const Cheb ch = cheb_coeffs(g[0]);
-  const double2 *b2 = reinterpret_cast<const double2 *>(b);
-  double2 s = b2[v];
-  for (int e = ptr[v]; e < ptr[v + 1]; ++e) {
-    const int w = idx[e];
-    const double2 xw = apply22(Dinv + 4 * int64_t(w), b2[w]);
-    const double *a = A + 4 * int64_t(e);
-    s.x -= (a[0] * xw.x + a[1] * xw.y) * ch.inv_theta;
-    s.y -= (a[2] * xw.x + a[3] * xw.y) * ch.inv_theta;
+  extern __shared__ double rsh[];   // [2][cols][2 (L + 1)]
+  const int nb = 2 * (L + 1);
+  const int64_t v0 = int64_t(blockIdx.x) * cols;
+  const int nv = int(V - v0 < int64_t(cols) ? V - v0 : int64_t(cols));
+  const float2 *W2 = reinterpret_cast<const float2 *>(W32);
+  for (int e = threadIdx.x; e < nv * nb; e += blockDim.x) {
+    const float2 w = W2[v0 * nb + e];
+    const double rv = r[v0 * nb + e];
+    rsh[e] = double(w.x) * rv;
+    rsh[cols * nb + e] = double(w.y) * rv;
   }
-  const double2 x1 = apply22(Dinv + 4 * int64_t(v), b2[v]);
-  const double2 ds = apply22(Dinv + 4 * int64_t(v), s);
-  const double x1x = x1.x * ch.inv_theta, x1y = x1.y * ch.inv_theta;
-  reinterpret_cast<double2 *>(x)[v] = make_double2(x1x + (ch.c1 * x1x + ch.c2 * ds.x), x1y + (ch.c1 * x1y + ch.c2 * ds.y));
-}
-
-__global__ __launch_bounds__(256) void resid_kernel(int n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                                    const double *__restrict__ A, const double *__restrict__ b,
-                                                    const double *__restrict__ x, double *__restrict__ r) {
-  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const double2 *x2 = reinterpret_cast<const double2 *>(x);
-  double2 s = reinterpret_cast<const double2 *>(b)[v];
-  for (int e = ptr[v]; e < ptr[v + 1]; ++e) {
-    const double2 xw = x2[idx[e]];
-    const double *a = A + 4 * int64_t(e);
-    s.x -= a[0] * xw.x + a[1] * xw.y;
-    s.y -= a[2] * xw.x + a[3] * xw.y;
+  __syncthreads();
+  for (int t = threadIdx.x; t < 2 * nv; t += blockDim.x) {
+    const int v = t >> 1, c = t & 1;
+    const double *p = rsh + c * cols * nb + v * nb;
+    double sum = 0.0;
+    for (int q = 0; q < nb; ++q) sum += p[q];
+    b0[2 * (v0 + v) + c] = sum;
   }
-  reinterpret_cast<double2 *>(r)[v] = s;
 }
 
-__global__ __launch_bounds__(256) void restrict_kernel(int n_c, const int32_t *__restrict__ mptr,
-                                                       const int32_t *__restrict__ midx, const double *__restrict__ r,
-                                                       double *__restrict__ bc) {
-  const int a = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (a >= n_c) return;
-  const double2 *r2 = reinterpret_cast<const double2 *>(r);
+// The V-cycle's kernels.  The first plane level smooths with Chebyshev of degree 2 (x kept
+// between the steps), the coarser ones with degree 1, whose pre-smoothed value from zero,
+// x1 = D^-1 b / theta, is formed wherever it is needed instead of stored.  A vertex's row
+// blocks are taken by G = 8 lanes (consecutive blocks, coalesced 32-byte loads) and summed
+// with shuffles; the restriction takes one wave per aggregate.
+constexpr int G = 8;
+
+// x1 of vertex w: D_w^-1 b_w / theta
+__device__ __forceinline__ double2 x1_of(const LevelDev &P, int w, double inv_theta) {
+  const double2 t = apply22(P.Dinv + 4 * int64_t(w), reinterpret_cast<const double2 *>(P.b)[w]);
+  return make_double2(t.x * inv_theta, t.y * inv_theta);
+}
+
+// partial sums of A_vw u_w over this lane's blocks of row v
+template <class U>
+__device__ __forceinline__ double2 row_partial(const LevelDev &P, int v, int sub, U u) {
   double2 s = make_double2(0.0, 0.0);
-  for (int i = mptr[a]; i < mptr[a + 1]; ++i) {
-    const double2 t = r2[midx[i]];
-    s.x += t.x;
-    s.y += t.y;
+  for (int e = P.ptr[v] + sub; e < P.ptr[v + 1]; e += G) {
+    const double2 xw = u(P.idx[e]);
+    const double4 a = reinterpret_cast<const double4 *>(P.A)[e];
+    s.x += a.x * xw.x + a.y * xw.y;
+    s.y += a.z * xw.x + a.w * xw.y;
   }
-  reinterpret_cast<double2 *>(bc)[a] = s;
+  return s;
 }
 
-// Prolongation and the first post-smoothing step: x' = x + xc[agg], d = D^-1 (b - A x') / theta,
-// x2 = x' + d (x' of the neighbours formed on the fly).
-__global__ __launch_bounds__(256) void cheb_post0_kernel(int n, const int32_t *__restrict__ ptr,
-                                                         const int32_t *__restrict__ idx, const double *__restrict__ A,
-                                                         const double *__restrict__ Dinv, const double *__restrict__ g,
-                                                         const double *__restrict__ b, const double *__restrict__ x,
-                                                         const int32_t *__restrict__ agg, const double *__restrict__ xc,
-                                                         double *__restrict__ x2, double *__restrict__ d) {
-  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const Cheb ch = cheb_coeffs(g[0]);
-  const double2 *xv2 = reinterpret_cast<const double2 *>(x);
-  const double2 *xc2 = reinterpret_cast<const double2 *>(xc);
-  double2 s = reinterpret_cast<const double2 *>(b)[v];
-  for (int e = ptr[v]; e < ptr[v + 1]; ++e) {
-    const int w = idx[e];
-    const double2 xw = xv2[w], cw = xc2[agg[w]];
-    const double ux = xw.x + cw.x, uy = xw.y + cw.y;
-    const double *a = A + 4 * int64_t(e);
-    s.x -= a[0] * ux + a[1] * uy;
-    s.y -= a[2] * ux + a[3] * uy;
+__device__ __forceinline__ double2 group_sum(double2 s) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    s.x += __shfl_xor(s.x, off, G);
+    s.y += __shfl_xor(s.y, off, G);
   }
-  const double2 xo = xv2[v], co = xc2[agg[v]];
-  const double2 dv = apply22(Dinv + 4 * int64_t(v), s);
-  const double dx = dv.x * ch.inv_theta, dy = dv.y * ch.inv_theta;
-  reinterpret_cast<double2 *>(x2)[v] = make_double2((xo.x + co.x) + dx, (xo.y + co.y) + dy);
-  reinterpret_cast<double2 *>(d)[v] = make_double2(dx, dy);
+  return s;
 }
 
-// Second post-smoothing step: x = x2 + c1 d + c2 D^-1 (b - A x2).
-__global__ __launch_bounds__(256) void cheb_post1_kernel(int n, const int32_t *__restrict__ ptr,
-                                                         const int32_t *__restrict__ idx, const double *__restrict__ A,
-                                                         const double *__restrict__ Dinv, const double *__restrict__ g,
-                                                         const double *__restrict__ b, const double *__restrict__ x2,
-                                                         const double *__restrict__ d, double *__restrict__ x) {
-  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const Cheb ch = cheb_coeffs(g[0]);
-  const double2 *xv2 = reinterpret_cast<const double2 *>(x2);
-  double2 s = reinterpret_cast<const double2 *>(b)[v];
-  for (int e = ptr[v]; e < ptr[v + 1]; ++e) {
-    const double2 xw = xv2[idx[e]];
-    const double *a = A + 4 * int64_t(e);
-    s.x -= a[0] * xw.x + a[1] * xw.y;
-    s.y -= a[2] * xw.x + a[3] * xw.y;
+// Degree-2 pre-smoothing from x = 0 on the first level: x1 = D^-1 b / theta,
+// x = x1 + c1 x1 + c2 D^-1 (b - A x1).
+__global__ __launch_bounds__(256) void pre2_kernel(const LevelDev *__restrict__ lv, int l) {
+  const LevelDev P = lv[l];
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int v = int(gid / G), sub = int(gid % G);
+  const Cheb ch = cheb_coeffs(P.g[0]);
+  double2 s = make_double2(0.0, 0.0);
+  if (v < P.n) s = row_partial(P, v, sub, [&](int w) { return x1_of(P, w, ch.inv_theta); });
+  s = group_sum(s);
+  if (v < P.n && sub == 0) {
+    const double2 b = reinterpret_cast<const double2 *>(P.b)[v];
+    const double2 ds = apply22(P.Dinv + 4 * int64_t(v), make_double2(b.x - s.x, b.y - s.y));
+    const double2 x1 = x1_of(P, v, ch.inv_theta);
+    reinterpret_cast<double2 *>(P.x)[v] =
+        make_double2(x1.x + (ch.c1 * x1.x + ch.c2 * ds.x), x1.y + (ch.c1 * x1.y + ch.c2 * ds.y));
   }
-  const double2 ds = apply22(Dinv + 4 * int64_t(v), s);
-  const double2 dv = reinterpret_cast<const double2 *>(d)[v];
-  const double2 xo = xv2[v];
-  reinterpret_cast<double2 *>(x)[v] = make_double2(xo.x + (ch.c1 * dv.x + ch.c2 * ds.x), xo.y + (ch.c1 * dv.y + ch.c2 * ds.y));
 }
 
-// x = Ainv b on the coarsest level (column-major inverse, one thread per row)
-__global__ __launch_bounds__(NC_MAX) void coarse_solve_kernel(int nc, const double *__restrict__ Ainv,
-                                                              const double *__restrict__ b, double *__restrict__ x) {
-  const int i = threadIdx.x;
-  if (i >= nc) return;
-  double s = 0.0;
-  for (int j = 0; j < nc; ++j) s += Ainv[int64_t(j) * nc + i] * b[j];
-  x[i] = s;
+// Residual and restriction in one pass, one wave per aggregate a of the next level:
+// b_C[a] = sum over the members v of (b_v - A_v x), x the pre-smoothed vector (stored for
+// degree 2, x1 formed on the fly for degree 1).  Lanes take (member, block) pairs, 8 members
+// and 8 blocks per pass.
+template <int DEG>
+__global__ __launch_bounds__(256) void resid_restrict_kernel(const LevelDev *__restrict__ lv, int l) {
+  const LevelDev P = lv[l], C = lv[l + 1];
+  const int a = int((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63, mi = lane / G, sub = lane % G;
+  double2 s = make_double2(0.0, 0.0);
+  if (a < C.n) {
+    const double inv_theta = DEG == 2 ? 0.0 : cheb_coeffs(P.g[0]).inv_theta;
+    const double2 *x2 = reinterpret_cast<const double2 *>(P.x);
+    for (int i = P.mptr[a] + mi; i < P.mptr[a + 1]; i += 64 / G) {
+      const int v = P.midx[i];
+      double2 t;
+      if constexpr (DEG == 2) t = row_partial(P, v, sub, [&](int w) { return x2[w]; });
+      else t = row_partial(P, v, sub, [&](int w) { return x1_of(P, w, inv_theta); });
+      if (sub == 0) {
+        const double2 b = reinterpret_cast<const double2 *>(P.b)[v];
+        t.x -= b.x;
+        t.y -= b.y;
+      }
+      s.x -= t.x;
+      s.y -= t.y;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s.x += __shfl_xor(s.x, off, 64);
+    s.y += __shfl_xor(s.y, off, 64);
+  }
+  if (a < C.n && lane == 0) reinterpret_cast<double2 *>(C.b)[a] = s;
+}
+
+// Prolongation and the first post-smoothing step: x' = x + x_C[agg], d = D^-1 (b - A x') / theta,
+// x_out = x' + d (x' of the neighbours formed on the fly; x is x1 for degree 1).  Degree 2
+// writes x2 and d for the second step; degree 1 writes the level's final x.
+template <int DEG>
+__global__ __launch_bounds__(256) void post0_kernel(const LevelDev *__restrict__ lv, int l) {
+  const LevelDev P = lv[l], C = lv[l + 1];
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int v = int(gid / G), sub = int(gid % G);
+  const Cheb ch = cheb_coeffs(P.g[0]);
+  const double2 *xv2 = reinterpret_cast<const double2 *>(P.x);
+  const double2 *xc2 = reinterpret_cast<const double2 *>(C.x);
+  auto xp = [&](int w) {
+    const double2 xw = DEG == 2 ? xv2[w] : x1_of(P, w, ch.inv_theta);
+    const double2 cw = xc2[P.agg[w]];
+    return make_double2(xw.x + cw.x, xw.y + cw.y);
+  };
+  double2 s = make_double2(0.0, 0.0);
+  if (v < P.n) s = row_partial(P, v, sub, xp);
+  s = group_sum(s);
+  if (v < P.n && sub == 0) {
+    const double2 b = reinterpret_cast<const double2 *>(P.b)[v];
+    const double2 dv = apply22(P.Dinv + 4 * int64_t(v), make_double2(b.x - s.x, b.y - s.y));
+    const double dx = dv.x * ch.inv_theta, dy = dv.y * ch.inv_theta;
+    const double2 xo = xp(v);
+    const double2 out = make_double2(xo.x + dx, xo.y + dy);
+    if constexpr (DEG == 2) {
+      reinterpret_cast<double2 *>(P.x2)[v] = out;
+      reinterpret_cast<double2 *>(P.d)[v] = make_double2(dx, dy);
+    } else {
+      reinterpret_cast<double2 *>(P.x)[v] = out;
+    }
+  }
+}
+
+// Second degree-2 post-smoothing step: x = x2 + c1 d + c2 D^-1 (b - A x2).
+__global__ __launch_bounds__(256) void post1_kernel(const LevelDev *__restrict__ lv, int l) {
+  const LevelDev P = lv[l];
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int v = int(gid / G), sub = int(gid % G);
+  const Cheb ch = cheb_coeffs(P.g[0]);
+  const double2 *xv2 = reinterpret_cast<const double2 *>(P.x2);
+  double2 s = make_double2(0.0, 0.0);
+  if (v < P.n) s = row_partial(P, v, sub, [&](int w) { return xv2[w]; });
+  s = group_sum(s);
+  if (v < P.n && sub == 0) {
+    const double2 b = reinterpret_cast<const double2 *>(P.b)[v];
+    const double2 ds = apply22(P.Dinv + 4 * int64_t(v), make_double2(b.x - s.x, b.y - s.y));
+    const double2 dv = reinterpret_cast<const double2 *>(P.d)[v];
+    const double2 xo = xv2[v];
+    reinterpret_cast<double2 *>(P.x)[v] =
+        make_double2(xo.x + (ch.c1 * dv.x + ch.c2 * ds.x), xo.y + (ch.c1 * dv.y + ch.c2 * ds.y));
+  }
+}
+
+// x = Ainv b on the coarsest level: one wave per row of the row-major inverse, lanes over its
+// columns, a shuffle sum per row.
+__global__ __launch_bounds__(1024) void coarse_solve_kernel(const LevelDev *__restrict__ lv, int last,
+                                                            const double *__restrict__ Ainv) {
+  const LevelDev C = lv[last];
+  const int nc = 2 * C.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  for (int i = wave; i < nc; i += nwave) {
+    double sum = 0.0;
+    for (int j = lane; j < nc; j += 64) sum += Ainv[int64_t(i) * nc + j] * C.b[j];
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (lane == 0) C.x[i] = sum;
+  }
 }
 
 unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
@@ -462,9 +535,9 @@ static void free_mdsc(fo_mdsc *p) {
   auto F = [](void *q) { if (q) (void)hipFree(q); };
   for (PlaneLevel &l : p->lv) {
     F(l.own_ptr); F(l.own_idx); F(l.diag); F(l.A); F(l.Dinv); F(l.bound); F(l.g); F(l.agg);
-    F(l.mptr); F(l.midx); F(l.gptr); F(l.gidx); F(l.b); F(l.x); F(l.x2); F(l.d); F(l.r);
+    F(l.mptr); F(l.midx); F(l.gptr); F(l.gidx); F(l.b); F(l.x); F(l.x2); F(l.d);
   }
-  F(p->blk_row); F(p->fac); F(p->W); F(p->JP); F(p->Ainv); F(p->flag);
+  F(p->blk_row); F(p->lv_dev); F(p->fac); F(p->W); F(p->W32); F(p->JP); F(p->Ainv); F(p->flag);
   if (p->flag_host) (void)hipHostFree(p->flag_host);
   delete p;
 }
@@ -542,7 +615,7 @@ extern "C" fo_status fo_mdsc_create(const fo_mesh *m, void *stream, fo_mdsc **ou
     if (l < last) {
       const PlaneTables &t = tabs[l];
       ok = ok && dev_alloc(q.Dinv, 4 * size_t(q.n)) && dev_alloc(q.bound, size_t(q.n)) && dev_alloc(q.g, 1) &&
-           dev_alloc(q.x2, 2 * size_t(q.n)) && dev_alloc(q.d, 2 * size_t(q.n)) && dev_alloc(q.r, 2 * size_t(q.n)) &&
+           (l > 0 || (dev_alloc(q.x2, 2 * size_t(q.n)) && dev_alloc(q.d, 2 * size_t(q.n)))) &&
            upload(q.agg, q.agg_h, s) && upload(q.mptr, t.mptr, s) && upload(q.midx, t.midx, s) &&
            upload(q.gptr, t.gptr, s) && upload(q.gidx, t.gidx, s);
     }
@@ -553,9 +626,16 @@ extern "C" fo_status fo_mdsc_create(const fo_mesh *m, void *stream, fo_mdsc **ou
     for (int32_t e = ptr[v]; e < ptr[v + 1]; ++e) blk_row[e] = v;
   const size_t nodes = size_t(V) * size_t(L + 1);
   const int nc = 2 * p->lv[last].n;
-  p->jp_count = std::max(size_t(2 * (L + 1)) * 2 * size_t(ptr[V]), 4 * nodes);   // also the weights' scratch
-  if (!upload(p->blk_row, blk_row, s) || !dev_alloc(p->fac, 12 * nodes) || !dev_alloc(p->W, 4 * nodes) ||
-      !dev_alloc(p->JP, p->jp_count) || !dev_alloc(p->Ainv, size_t(nc) * nc) || !dev_alloc(p->flag, N_FLAGS))
+  p->jp_count = size_t(2 * (L + 1)) * 2 * size_t(ptr[V]);
+  // device views of the levels
+  std::vector<LevelDev> views(p->lv.size());
+  for (size_t l = 0; l <= last; ++l) {
+    const PlaneLevel &q = p->lv[l];
+    views[l] = LevelDev{q.n, q.ptr, q.idx, q.agg, q.mptr, q.midx, q.A, q.Dinv, q.g, q.b, q.x, q.x2, q.d};
+  }
+  if (!upload(p->blk_row, blk_row, s) || !upload(p->lv_dev, views, s) || !dev_alloc(p->fac, 12 * nodes) ||
+      !dev_alloc(p->W, 4 * nodes) || !dev_alloc(p->W32, 4 * nodes) || !dev_alloc(p->JP, p->jp_count) ||
+      !dev_alloc(p->Ainv, size_t(nc) * nc) || !dev_alloc(p->flag, N_FLAGS))
     return bail(FO_ENOMEM, "fo_mdsc_create: device allocation failed");
   if (hipHostMalloc(reinterpret_cast<void **>(&p->flag_host), sizeof(int32_t) * N_FLAGS) != hipSuccess)
     return bail(FO_ENOMEM, "fo_mdsc_create: pinned allocation failed");
@@ -590,10 +670,19 @@ fo_status setup_t(fo_mdsc *p, const JT *J, hipStream_t s) {
   const fo_mesh *m = p->mesh;
   const MeshView &mv = m->view;
   const PlaneLevel &l0 = p->lv[0];
-  hipLaunchKernelGGL(weights_kernel<JT>, dim3(blocks_for(mv.V, 128)), dim3(128), 0, s, mv, m->self_rank, J, p->W, p->JP);
+  // columns per block: the block's weights and factors (8 (L+1) doubles per column) within 64 KB of LDS
+  const size_t col_bytes = size_t(8) * (mv.L + 1) * sizeof(double);
+  int cols = 64;
+  while (cols > 1 && cols * col_bytes > 65536) cols /= 2;
+  hipLaunchKernelGGL(weights_kernel<JT>, dim3(blocks_for(mv.V, cols)), dim3(cols), cols * col_bytes, s, mv,
+                     m->self_rank, J, p->W, p->W32);
   FO_LAUNCH_CHECK("mdsc weights");
-  hipLaunchKernelGGL(plane_kernel<JT>, dim3(blocks_for(l0.nnzb, 256)), dim3(256), 0, s, mv, m->nbr_ptr, m->nbr_idx,
-                     p->blk_row, l0.nnzb, J, p->W, p->JP, l0.A);
+  // blocks per workgroup: their J P0 rows (4 (L+1) floats each) within 64 KB of LDS
+  const size_t blk_bytes = size_t(4) * (mv.L + 1) * sizeof(float);
+  int tpb = 256;
+  while (tpb > 1 && tpb * blk_bytes > 65536) tpb /= 2;
+  hipLaunchKernelGGL(plane_kernel<JT>, dim3(blocks_for(l0.nnzb, tpb)), dim3(tpb), tpb * blk_bytes, s, mv, m->nbr_ptr,
+                     m->nbr_idx, p->blk_row, l0.nnzb, J, p->W, p->JP, l0.A);
   FO_LAUNCH_CHECK("mdsc plane");
   return FO_OK;
 }
@@ -644,31 +733,39 @@ extern "C" fo_status fo_mdsc_apply(const fo_mdsc *p, const double *r, double *z,
   const MeshView &mv = p->mesh->view;
   const size_t last = p->lv.size() - 1;
   const PlaneLevel &l0 = p->lv[0];
-  hipLaunchKernelGGL(restrict_fine_kernel, dim3(blocks_for(2 * int64_t(mv.V), 256)), dim3(256), 0, s, mv.V, mv.L, p->W,
-                     r, l0.b);
-  FO_LAUNCH_CHECK("mdsc restrict");
-  for (size_t l = 0; l < last; ++l) {
-    const PlaneLevel &q = p->lv[l];
-    const unsigned gb = blocks_for(q.n, 256);
-    hipLaunchKernelGGL(cheb_pre_kernel, dim3(gb), dim3(256), 0, s, q.n, q.ptr, q.idx, q.A, q.Dinv, q.g, q.b, q.x);
-    hipLaunchKernelGGL(resid_kernel, dim3(gb), dim3(256), 0, s, q.n, q.ptr, q.idx, q.A, q.b, q.x, q.r);
-    const PlaneLevel &c = p->lv[l + 1];
-    hipLaunchKernelGGL(restrict_kernel, dim3(blocks_for(c.n, 256)), dim3(256), 0, s, c.n, q.mptr, q.midx, q.r, c.b);
+  {
+    const size_t col_bytes = size_t(4) * (mv.L + 1) * sizeof(double);
+    int cols = 64;
+    while (cols > 1 && cols * col_bytes > 65536) cols /= 2;
+    hipLaunchKernelGGL(restrict_fine_kernel, dim3(blocks_for(mv.V, cols)), dim3(128), cols * col_bytes, s, mv.V,
+                       mv.L, cols, p->W32, r, l0.b);
+    FO_LAUNCH_CHECK("mdsc restrict");
+  }
+  // level 0 smooths with degree 2, the coarser levels with degree 1
+  const int nl = int(last);
+  for (int l = 0; l < nl; ++l) {
+    const unsigned gv = blocks_for(int64_t(p->lv[l].n) * G, 256), ga = blocks_for(int64_t(p->lv[l + 1].n) * 64, 256);
+    if (l == 0) {
+      hipLaunchKernelGGL(pre2_kernel, dim3(gv), dim3(256), 0, s, p->lv_dev, l);
+      hipLaunchKernelGGL(resid_restrict_kernel<2>, dim3(ga), dim3(256), 0, s, p->lv_dev, l);
+    } else {
+      hipLaunchKernelGGL(resid_restrict_kernel<1>, dim3(ga), dim3(256), 0, s, p->lv_dev, l);
+    }
     FO_LAUNCH_CHECK("mdsc pre-smoothing");
   }
-  const PlaneLevel &cl = p->lv[last];
-  hipLaunchKernelGGL(coarse_solve_kernel, dim3(1), dim3(NC_MAX), 0, s, 2 * cl.n, p->Ainv, cl.b, cl.x);
+  hipLaunchKernelGGL(coarse_solve_kernel, dim3(1), dim3(1024), 0, s, p->lv_dev, nl, p->Ainv);
   FO_LAUNCH_CHECK("mdsc coarse solve");
-  for (size_t l = last; l-- > 0;) {
-    const PlaneLevel &q = p->lv[l];
-    const unsigned gb = blocks_for(q.n, 256);
-    hipLaunchKernelGGL(cheb_post0_kernel, dim3(gb), dim3(256), 0, s, q.n, q.ptr, q.idx, q.A, q.Dinv, q.g, q.b, q.x,
-                       q.agg, p->lv[l + 1].x, q.x2, q.d);
-    hipLaunchKernelGGL(cheb_post1_kernel, dim3(gb), dim3(256), 0, s, q.n, q.ptr, q.idx, q.A, q.Dinv, q.g, q.b, q.x2,
-                       q.d, q.x);
+  for (int l = nl - 1; l >= 0; --l) {
+    const unsigned gv = blocks_for(int64_t(p->lv[l].n) * G, 256);
+    if (l == 0) {
+      hipLaunchKernelGGL(post0_kernel<2>, dim3(gv), dim3(256), 0, s, p->lv_dev, l);
+      hipLaunchKernelGGL(post1_kernel, dim3(gv), dim3(256), 0, s, p->lv_dev, l);
+    } else {
+      hipLaunchKernelGGL(post0_kernel<1>, dim3(gv), dim3(256), 0, s, p->lv_dev, l);
+    }
     FO_LAUNCH_CHECK("mdsc post-smoothing");
   }
-  return colblock_apply_correction(p->mesh, p->fac, p->W, p->JP, l0.x, r, z, s);
+  return colblock_apply_correction(p->mesh, p->fac, p->W32, p->JP, l0.x, r, z, s);
 }
 
 extern "C" fo_status fo_mdsc_export(const fo_mdsc *p, int32_t what, int32_t level, double *host, size_t count,

@@ -8,8 +8,8 @@ fo_status spmv(const fo_mesh *mesh, const void *vals, int dtype, const double *x
 fo_status colblock_factor(const fo_mesh *mesh, const void *vals, int dtype, float *fac, hipStream_t s);
 fo_status colblock_apply(const fo_mesh *mesh, const float *fac, const double *r, double *z, hipStream_t s);
 // z = P0 y + M^{-1} (r - JP y): the column smoother after the plane correction of the two-level
-// preconditioner (W: collapse weights [V][L+1][2][2], JP: J P0 by column, y: [2 V])
-fo_status colblock_apply_correction(const fo_mesh *mesh, const float *fac, const double *W, const double *JP,
+// preconditioner (W32: FP32 collapse weights [V][L+1][2][2], JP: FP32 J P0 by column, y: [2 V])
+fo_status colblock_apply_correction(const fo_mesh *mesh, const float *fac, const float *W32, const float *JP,
                                     const double *y, const double *r, double *z, hipStream_t s);
 int multidot_blocks(int64_t n);
 // out[0..nv-1] = V_i . w, out[nv] = w . w (partial: multidot_blocks(n) * (nv + 1) doubles;

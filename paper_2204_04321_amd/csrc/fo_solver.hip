@@ -19,7 +19,8 @@ __device__ __forceinline__ int nlev(int k, int L) { return (k == 0 || k == L) ? 
 __device__ __forceinline__ int cumlev(int k) { return k == 0 ? 0 : 3 * k - 1; }
 
 constexpr int SPMV_LANES = 8;   // lanes per node (pair of rows)
-constexpr int APPLY_MAX_THREADS = 64;   // columns per preconditioner-apply block
+constexpr int APPLY_MAX_COLS = 64;      // columns per preconditioner-apply block
+constexpr int APPLY_THREADS = 256;      // its threads: all stage and copy, one per column sweeps
 
 template <class JT> struct Pair2;
 template <> struct Pair2<double> { using T = double2; };
@@ -204,16 +205,17 @@ __device__ __forceinline__ void column_sweep(const float *__restrict__ fac, int6
   }
 }
 
-// z = M^{-1} r for every vertical line.  A block's columns are contiguous in r and z
-// (2 (L+1) values each): they are copied through LDS with coalesced loads and stores, and
-// each thread runs its column's two sweeps in place in LDS.
-__global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V, int L, const float *__restrict__ fac,
-                                                                           const double *__restrict__ r,
-                                                                           double *__restrict__ z) {
-  extern __shared__ double col_sh[];   // [blockDim.x][2 (L + 1)]
+// z = M^{-1} r for every vertical line.  A block's `cols` columns are contiguous in r and z
+// (2 (L+1) values each): all its threads copy them through LDS with coalesced loads and
+// stores, and one thread per column runs the column's two sweeps in place in LDS.
+__global__ __launch_bounds__(APPLY_THREADS) void colblock_apply_kernel(int V, int L, int cols,
+                                                                       const float *__restrict__ fac,
+                                                                       const double *__restrict__ r,
+                                                                       double *__restrict__ z) {
+  extern __shared__ double col_sh[];   // [cols][2 (L + 1)]
   const int n = 2 * (L + 1);
-  const int64_t v0 = int64_t(blockIdx.x) * blockDim.x;
-  const int nv = int(V - v0 < int64_t(blockDim.x) ? V - v0 : int64_t(blockDim.x));
+  const int64_t v0 = int64_t(blockIdx.x) * cols;
+  const int nv = int(V - v0 < int64_t(cols) ? V - v0 : int64_t(cols));
   for (int e = threadIdx.x; e < nv * n; e += blockDim.x) col_sh[e] = r[v0 * n + e];
   __syncthreads();
   if (int(threadIdx.x) < nv) column_sweep(fac, V, L, v0 + threadIdx.x, col_sh + threadIdx.x * n);
@@ -222,40 +224,41 @@ __global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_apply_kernel(int V
 }
 
 // The last step of the two-level preconditioner: z = P0 y + M^{-1} (r - (J P0) y).  While the
-// block's columns are staged in LDS each row subtracts its row of J P0 (2 D values: column v's
-// rows of J P0 follow each other, 2 (L+1) rows of 2 D values, entry (r, d) at 2 r + d, the
-// block of v starting at 4 (L+1) nbr_ptr[v]) against the plane vector y; after the sweeps each
-// row adds its prolongation sum_c W[v][k][c'][c] y[(v, c)].
-__global__ __launch_bounds__(APPLY_MAX_THREADS) void colblock_correction_kernel(
-    int V, int L, const int32_t *__restrict__ nbr_ptr, const int32_t *__restrict__ nbr_idx,
-    const float *__restrict__ fac, const double *__restrict__ W, const double *__restrict__ JP,
+// block's columns are staged in LDS each row subtracts its row of J P0 against the plane vector
+// y (J P0 in FP32, column v's block starting at 4 (L+1) nbr_ptr[v] and holding entry (r, d) of
+// row q at (2 r + d) 2 (L+1) + q, so consecutive rows of a column are consecutive for each
+// entry); after the sweeps each row adds its prolongation sum_c W[v][k][c'][c] y[(v, c)] (FP32
+// weights, the two c of a row next to each other).
+__global__ __launch_bounds__(APPLY_THREADS) void colblock_correction_kernel(
+    int V, int L, int cols, const int32_t *__restrict__ nbr_ptr, const int32_t *__restrict__ nbr_idx,
+    const float *__restrict__ fac, const float *__restrict__ W32, const float *__restrict__ JP,
     const double *__restrict__ y, const double *__restrict__ r, double *__restrict__ z) {
-  extern __shared__ double col_sh[];   // [blockDim.x][2 (L + 1)]
+  extern __shared__ double col_sh[];   // [cols][2 (L + 1)]
   const int n = 2 * (L + 1);
-  const int64_t v0 = int64_t(blockIdx.x) * blockDim.x;
-  const int nv = int(V - v0 < int64_t(blockDim.x) ? V - v0 : int64_t(blockDim.x));
+  const int64_t v0 = int64_t(blockIdx.x) * cols;
+  const int nv = int(V - v0 < int64_t(cols) ? V - v0 : int64_t(cols));
   const double2 *y2 = reinterpret_cast<const double2 *>(y);
   for (int e = threadIdx.x; e < nv * n; e += blockDim.x) {
     const int64_t v = v0 + e / n;
     const int q = e - (e / n) * n;
     const int p0 = nbr_ptr[v], D = nbr_ptr[v + 1] - p0;
-    const double *jp = JP + int64_t(2 * n) * p0 + int64_t(q) * 2 * D;
+    const float *jp = JP + int64_t(2 * n) * p0 + q;
     double s = r[v0 * n + e];
     for (int i = 0; i < D; ++i) {
       const double2 yw = y2[nbr_idx[p0 + i]];
-      s -= jp[2 * i] * yw.x + jp[2 * i + 1] * yw.y;
+      s -= double(jp[(2 * i) * n]) * yw.x + double(jp[(2 * i + 1) * n]) * yw.y;
     }
     col_sh[e] = s;
   }
   __syncthreads();
   if (int(threadIdx.x) < nv) column_sweep(fac, V, L, v0 + threadIdx.x, col_sh + threadIdx.x * n);
   __syncthreads();
+  const float2 *W2 = reinterpret_cast<const float2 *>(W32);
   for (int e = threadIdx.x; e < nv * n; e += blockDim.x) {
     const int64_t v = v0 + e / n;
-    const int q = e - (e / n) * n;
-    const double *wq = W + (v * (L + 1) + (q >> 1)) * 4 + 2 * (q & 1);
+    const float2 w = W2[v0 * n + e];
     const double2 yv = y2[v];
-    z[v0 * n + e] = col_sh[e] + (wq[0] * yv.x + wq[1] * yv.y);
+    z[v0 * n + e] = col_sh[e] + (double(w.x) * yv.x + double(w.y) * yv.y);
   }
 }
 
@@ -412,6 +415,14 @@ __global__ __launch_bounds__(256) void xpay_kernel(int64_t n, const double *__re
     z[p] = x[p] + a * y[p];
 }
 
+// columns per apply block: the block's columns (2 (L+1) doubles each) stay within 64 KB of LDS
+size_t col_bytes(int L) { return size_t(2) * (L + 1) * sizeof(double); }
+int apply_cols(int L) {
+  int cols = APPLY_MAX_COLS;
+  while (cols > 1 && cols * col_bytes(L) > 65536) cols /= 2;
+  return cols;
+}
+
 unsigned grid_for(int64_t n, int block) {
   const int64_t g = (n + block - 1) / block;
   return unsigned(g < 4096 ? (g > 0 ? g : 1) : 4096);
@@ -448,25 +459,21 @@ fo_status colblock_factor(const fo_mesh *mesh, const void *vals, int dtype, floa
 
 fo_status colblock_apply(const fo_mesh *mesh, const float *fac, const double *r, double *z, hipStream_t s) {
   const MeshView &m = mesh->view;
-  // columns per block: the block's columns (2 (L+1) doubles each) stay within 64 KB of LDS
-  const size_t col_bytes = size_t(2) * (m.L + 1) * sizeof(double);
-  int tpb = APPLY_MAX_THREADS;
-  while (tpb > 1 && tpb * col_bytes > 65536) tpb /= 2;
-  const unsigned blocks = unsigned((m.V + tpb - 1) / tpb);
-  hipLaunchKernelGGL(colblock_apply_kernel, dim3(blocks), dim3(tpb), tpb * col_bytes, s, m.V, m.L, fac, r, z);
+  const int cols = apply_cols(m.L);
+  const unsigned blocks = unsigned((m.V + cols - 1) / cols);
+  hipLaunchKernelGGL(colblock_apply_kernel, dim3(blocks), dim3(APPLY_THREADS), cols * col_bytes(m.L), s, m.V, m.L,
+                     cols, fac, r, z);
   FO_LAUNCH_CHECK("colblock_apply_kernel");
   return FO_OK;
 }
 
-fo_status colblock_apply_correction(const fo_mesh *mesh, const float *fac, const double *W, const double *JP,
+fo_status colblock_apply_correction(const fo_mesh *mesh, const float *fac, const float *W32, const float *JP,
                                     const double *y, const double *r, double *z, hipStream_t s) {
   const MeshView &m = mesh->view;
-  const size_t col_bytes = size_t(2) * (m.L + 1) * sizeof(double);
-  int tpb = APPLY_MAX_THREADS;
-  while (tpb > 1 && tpb * col_bytes > 65536) tpb /= 2;
-  const unsigned blocks = unsigned((m.V + tpb - 1) / tpb);
-  hipLaunchKernelGGL(colblock_correction_kernel, dim3(blocks), dim3(tpb), tpb * col_bytes, s, m.V, m.L, mesh->nbr_ptr,
-                     mesh->nbr_idx, fac, W, JP, y, r, z);
+  const int cols = apply_cols(m.L);
+  const unsigned blocks = unsigned((m.V + cols - 1) / cols);
+  hipLaunchKernelGGL(colblock_correction_kernel, dim3(blocks), dim3(APPLY_THREADS), cols * col_bytes(m.L), s, m.V,
+                     m.L, cols, mesh->nbr_ptr, mesh->nbr_idx, fac, W32, JP, y, r, z);
   FO_LAUNCH_CHECK("colblock_correction_kernel");
   return FO_OK;
 }

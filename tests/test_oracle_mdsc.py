@@ -222,6 +222,17 @@ def test_chebyshev_matches_its_error_polynomial():
             assert np.abs(got - (xs + e)).max() <= 1e-10 * np.abs(xs).max(), (deg, ratio)
 
 
+def _cheb_error_operator(A, Dinv, g, degree):
+    """p(D^-1 A) with p(t) = T_k((theta - t)/delta) / T_k(theta/delta) on [g/30, g]."""
+    n = A.shape[0]
+    lo = g / mdsc.CHEB_RATIO
+    theta, delta = 0.5 * (g + lo), 0.5 * (g - lo)
+    Y = (theta * np.eye(n) - Dinv @ A) / delta
+    Tk = np.polynomial.chebyshev.Chebyshev.basis(degree).convert(kind=np.polynomial.Polynomial).coef
+    P = sum(c * np.linalg.matrix_power(Y, i) for i, c in enumerate(Tk))
+    return P / np.polynomial.chebyshev.Chebyshev.basis(degree)(theta / delta)
+
+
 def test_vcycle_error_propagation(slab):
     """One smoothing level and an exact coarsest level: the V-cycle B satisfies
     I - B A = S (I - T A_c^-1 T^T A) S with S = p_2(D^-1 A) the smoother's error operator."""
@@ -243,6 +254,28 @@ def test_vcycle_error_propagation(slab):
     assert np.abs((np.eye(n) - B @ A) - E).max() <= 1e-9
 
 
+def test_vcycle_error_propagation_two_levels():
+    """Two smoothing levels (degree 2, then degree 1) above the exact coarsest level: the
+    recursion I - B_0 A_0 = S_0 (I - T_0 B_1 T_0^T A_0) S_0 with
+    I - B_1 A_1 = S_1 (I - T_1 A_c^-1 T_1^T A_1) S_1."""
+    m, U = _cap(600, seed=3, n_layers=1)
+    _, J = fo.assemble(m, U)
+    H = mdsc.Hierarchy(m, J.tocsr())
+    assert len(H.levels) == 2
+    l0, l1 = H.levels
+    A0, A1 = l0["A"].toarray(), l1["A"].toarray()
+    T0, T1 = l0["T"].toarray(), l1["T"].toarray()
+    S0 = _cheb_error_operator(A0, l0["Dinv"].toarray(), l0["g"], 2)
+    S1 = _cheb_error_operator(A1, l1["Dinv"].toarray(), l1["g"], 1)
+    Ac = T1.T @ A1 @ T1
+    n1 = A1.shape[0]
+    B1 = np.linalg.solve(A1.T, (np.eye(n1) - S1 @ (np.eye(n1) - T1 @ np.linalg.solve(Ac, T1.T @ A1)) @ S1).T).T
+    n0 = A0.shape[0]
+    E0 = S0 @ (np.eye(n0) - T0 @ B1 @ T0.T @ A0) @ S0
+    B = np.column_stack([H.vcycle(col) for col in np.eye(n0)])
+    assert np.abs((np.eye(n0) - B @ A0) - E0).max() <= 1e-8
+
+
 def test_apply_is_exact_on_the_coarse_range_and_for_column_operators(cap):
     m, J = cap
     rng = np.random.default_rng(5)
@@ -250,7 +283,7 @@ def test_apply_is_exact_on_the_coarse_range_and_for_column_operators(cap):
     # orthogonal to the coarse space, and an error in the range of P0 is removed exactly
     small, Us = _cap(60, seed=6, n_layers=4)
     _, Js = fo.assemble(small, Us)
-    H = mdsc.Hierarchy(small, Js)
+    H = mdsc.Hierarchy(small, Js, store=np.float64)
     assert not H.levels
     r = rng.normal(size=small.n_dofs)
     y = np.linalg.solve(H.A_coarse, H.P0.T @ r)
@@ -264,11 +297,14 @@ def test_apply_is_exact_on_the_coarse_range_and_for_column_operators(cap):
     C = sp.coo_matrix(J)
     keep = (C.row // nb) == (C.col // nb)
     Jc = sp.csr_matrix((C.data[keep], (C.row[keep], C.col[keep])), shape=J.shape)
-    Hc = mdsc.Hierarchy(m, Jc)
+    Hc = mdsc.Hierarchy(m, Jc, store=np.float64)
     assert Hc.levels
     r = rng.normal(size=m.n_dofs)
     want = sp.linalg.spsolve(Jc.tocsc(), r)
-    assert np.abs(Hc.apply(r) - want).max() <= 1e-5 * np.abs(want).max()
+    assert np.abs(Hc.apply(r) - want).max() <= 1e-9 * np.abs(want).max()
+    # with the parts stored in FP32 it stays the inverse to the FP32 rounding
+    Hc32 = mdsc.Hierarchy(m, Jc)
+    assert np.abs(Hc32.apply(r) - want).max() <= 1e-5 * np.abs(want).max()
 
 
 def test_two_level_cuts_gmres_iterations(cap):
