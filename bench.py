@@ -10,12 +10,14 @@ Prints one JSON line with cells/s, the roofline position of the assembly kernel
 FP64 vector peak), the measured HBM traffic when the committed counter figures match the
 kernel source, and the FP64 CPU oracle timed on a bounded sample.  Beside the headline,
 the same object carries the rest of the metric: the FP32-Jacobian assembly on the same mesh
-(jacobian_f32), one Newton solve on it (newton), and Newton wall time from the learned
-initial guess against the shallow-ice guess on held-out ice caps (learned_vs_plain).
+(jacobian_f32), one Newton solve on it with the column preconditioner (newton) and with the
+two-level column semicoarsening preconditioner (newton_two_level), and Newton wall time from
+the learned initial guess against the shallow-ice guess on held-out ice caps
+(learned_vs_plain).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 20] [--no-cpu] [--no-extra] [--jdtype f64|f32]
     python bench.py --workload ensemble     # 64-member batch in one persistent launch
-    python bench.py --workload newton       # Newton solves, FP64 and FP32 Jacobian values
+    python bench.py --workload newton [--precond column|mdsc]   # Newton solves, FP64 and FP32 Jacobian values
     python bench.py --workload marine       # marine ice sheet with ocean fronts and a floating shelf
     python bench.py --workload tet          # the ice-sheet mesh extruded to tetrahedra (3 per prism)
 """
@@ -361,27 +363,34 @@ def time_assembly(M, m, Ud, jdtype, steps, warmup):
             "ms_100": ms_100, "alg_bytes": alg, "achieved_gbs": alg / kern_s / 1e9}
 
 
-def newton_line(M):
+def newton_line(M, precond="column"):
     """One Newton solve on the ice-sheet mesh from the shallow-ice guess to tol 1e-8 (FP64
-    Jacobian values, GMRES with the column preconditioner), after an untimed first call."""
+    Jacobian values, GMRES with the column preconditioner or the two-level one), after an
+    untimed first call."""
     import torch
+    from paper_2204_04321_amd.api import Mdsc
+    kw = {}
+    if precond == "mdsc":
+        kw = {"preconditioner": "mdsc", "mdsc": Mdsc(M)}
     U = torch.zeros(M.n_dofs, dtype=torch.float64, device="cuda")
     opts = M.newton_opts(jac_dtype="f64")
     ws = torch.empty(M.workspace_bytes(opts), dtype=torch.uint8, device="cuda")
-    M.newton_solve(U, workspace=ws, init="sia", max_newton=1)
+    M.newton_solve(U, workspace=ws, init="sia", max_newton=1, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rep = M.newton_solve(U, workspace=ws, init="sia")
+    rep = M.newton_solve(U, workspace=ws, init="sia", **kw)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     del ws
+    name = ("the vertical-column block-LU preconditioner" if precond == "column"
+            else "the two-level column semicoarsening preconditioner")
     return {"wall_s": wall, "status": rep["status"], "newton_its": rep["newton_its"], "gmres_its": rep["lin_its"],
             "residual_calls": rep["residual_calls"], "jacobian_calls": rep["jacobian_calls"],
             "final_rel": rep["final_rel"], "ms_total_fill": rep["ms_total_fill"],
             "ms_prec_construction": rep["ms_prec_construction"], "ms_linear_solve": rep["ms_linear_solve"],
             "ms_total_solve": rep["ms_total_solve"],
-            "config": "ice-sheet wedge mesh, shallow-ice start, tol 1e-8 of ||F(0)||, GMRES(100) with the "
-                      "vertical-column block-LU preconditioner, lin_rtol 1e-6, FP64 Jacobian values"}
+            "config": "ice-sheet wedge mesh, shallow-ice start, tol 1e-8 of ||F(0)||, GMRES(100) with " + name
+                      + ", lin_rtol 1e-6, FP64 Jacobian values"}
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2204_04321_amd", "weights", "learned_guess.npz")
@@ -533,6 +542,9 @@ def main():
         out["newton"] = newton_line(M)
         print(f"[bench] Newton {out['newton']['wall_s']:.3f} s, {out['newton']['newton_its']} its",
               file=sys.stderr, flush=True)
+        out["newton_two_level"] = newton_line(M, "mdsc")
+        print(f"[bench] Newton (two-level preconditioner) {out['newton_two_level']['wall_s']:.3f} s, "
+              f"{out['newton_two_level']['gmres_its']} GMRES its", file=sys.stderr, flush=True)
     M.close()
     del Ud
     torch.cuda.empty_cache()
