@@ -72,3 +72,19 @@ def test_aggregation_rejects_malformed_graphs():
     for msg, (ptr, idx) in bad.items():
         with pytest.raises(FoError, match=re.escape(msg)):
             aggregate_graph(np.array(ptr), np.array(idx))
+
+
+def test_icesheet_aggregation_matches_the_oracle():
+    """The ice-sheet configuration's base graph (125k vertices): every level bit for bit."""
+    from fo_inputs import config1_icesheet
+    from paper_2204_04321_amd import aggregate_graph
+    m, _ = config1_icesheet()
+    nbrs = mdsc.plane_graph(m)
+    sizes = []
+    while len(nbrs) > mdsc.COARSEST_MAX:
+        want, n_want = mdsc.aggregate(nbrs)
+        got, n_got = aggregate_graph(*_csr(nbrs))
+        assert n_got == n_want and np.array_equal(got, want), len(nbrs)
+        sizes.append(len(nbrs))
+        nbrs = mdsc.coarse_graph(nbrs, want, n_want)
+    assert sizes[0] == m.n_verts and len(sizes) >= 3
