@@ -7,7 +7,7 @@ import pytest
 import scipy.sparse as sp
 import torch
 
-from fo_inputs import config0_slab, smooth_velocity
+from fo_inputs import config0_slab, smooth_velocity, structured_box
 from fo_inputs.meshgen import ExtrudedMesh, _dome_fields, ellipse_mesh
 from oracle import fo_oracle as fo
 from oracle import mdsc, solve
@@ -41,13 +41,37 @@ def _case(name):
         m = _cap(600, L=1, seed=3)
     elif name == "graded_sigma":
         m = _cap(500, L=8, seed=4, sigma=np.linspace(0, 1, 9) ** 1.7)
+    elif name in ("box_plane_64", "box_plane_65"):
+        # 64 base vertices: the whole plane is the coarsest level (its inverse has the largest
+        # size, 128 dofs); 65: one smoothing level above it
+        nx, ny = (7, 7) if name == "box_plane_64" else (4, 12)
+        xy, cells, sig = structured_box(nx, ny, 3, 20e3, 30e3, elem="wedge")
+        m = _slab_fields(xy, cells, sig, seed=6)
+    elif name == "islands_100":
+        # 100 separate triangles: every aggregate of the first coarse level is isolated, so the
+        # next level groups them 8 at a time
+        rng = np.random.default_rng(7)
+        base = np.array([[0.0, 0.0], [3e3, 0.0], [1e3, 2.5e3]])
+        xy = np.concatenate([base + np.array([10e3 * (i % 10), 10e3 * (i // 10)]) for i in range(100)])
+        xy += rng.uniform(-200.0, 200.0, xy.shape)
+        cells = np.arange(300, dtype=np.int32).reshape(100, 3)
+        m = _slab_fields(xy, cells, np.linspace(0, 1, 4), seed=8)
     else:
         raise KeyError(name)
     return m, solve.sia_guess(m) + smooth_velocity(m, np.random.default_rng(1), u_scale=5.0)
 
 
+def _slab_fields(xy, cells, sigma, seed):
+    rng = np.random.default_rng(seed)
+    x, y = xy[:, 0], xy[:, 1]
+    H = 800.0 + 100.0 * np.sin(x / 7e3) * np.cos(y / 9e3) + rng.uniform(-5.0, 5.0, len(x))
+    bed = -0.01 * x
+    beta = 1000.0 * (1.0 + 0.5 * np.sin(y / 5e3))
+    return ExtrudedMesh("wedge", xy, cells, bed + H, H, beta, sigma, A=1e-16)
+
+
 CASES = ["cap400_wedge", "cap3000_wedge_L10", "slab_hex", "cap400_tet", "tiny_exact_plane", "single_layer",
-         "graded_sigma"]
+         "graded_sigma", "box_plane_64", "box_plane_65", "islands_100"]
 
 
 def _oracle_levels(m):
