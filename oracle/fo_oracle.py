@@ -498,6 +498,8 @@ def assemble(mesh, U: np.ndarray, want_jac: bool = True, picard: bool = False,
     cplx = np.iscomplexobj(U)
     R = np.zeros(nd, dtype=complex if cplx else float)
     J = None
+    parts = []    # per chunk, the summed element entries (explicit zeros kept: the pattern is
+                  # every node pair of a cell, also pairs of a prism that share no tetrahedron)
     all_cells = np.arange(mesh.n_cells) if cells is None else np.asarray(cells)
     for ch in _chunks(all_cells.shape[0], chunk):
         ids = all_cells[ch]
@@ -512,11 +514,15 @@ def assemble(mesh, U: np.ndarray, want_jac: bool = True, picard: bool = False,
             m = dofs.shape[1]
             rows = np.repeat(dofs, m, axis=1).ravel()
             cols = np.tile(dofs, (1, m)).ravel()
-            Jc = sp.coo_matrix((Je.reshape(-1), (rows, cols)), shape=(nd, nd)).tocsr()
-            J = Jc if J is None else J + Jc
+            parts.append(sp.coo_matrix((Je.reshape(-1), (rows, cols)), shape=(nd, nd)).tocsr().tocoo())
     if _has_front(mesh):      # per node, independent of U: exact on any row whose cells are all included
         R += front_load(mesh)
     if want_jac and not cplx:
+        # one conversion of all chunks' entries: a sum of sparse matrices would drop the
+        # structural zeros
+        J = sp.coo_matrix((np.concatenate([q.data for q in parts]),
+                           (np.concatenate([q.row for q in parts]), np.concatenate([q.col for q in parts]))),
+                          shape=(nd, nd)).tocsr()
         J.sum_duplicates()
         J.sort_indices()
     return R, J

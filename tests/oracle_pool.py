@@ -16,10 +16,19 @@ _STATE = {}
 
 
 def init_worker(mesh_factory, files):
-    """Pool initializer: build the seeded mesh once per worker and map the GPU outputs."""
+    """Pool initializer: build the seeded mesh once per worker and map the GPU outputs.  A
+    mesh with ocean fronts has its front-face terms (independent of U) formed once here, and
+    the oracle's front_face_terms returns them for this mesh instead of recomputing them for
+    every column range."""
     from threadpoolctl import threadpool_limits
+
+    from oracle import fo_oracle as fo
     threadpool_limits(limits=1)
     m, U = mesh_factory()
+    if fo._has_front(m):
+        terms = fo.front_face_terms(m)
+        original = fo.front_face_terms
+        fo.front_face_terms = lambda mesh: terms if mesh is m else original(mesh)
     _STATE.update(m=m, U=U, **{k: np.load(v, mmap_mode="r") for k, v in files.items()})
 
 
@@ -84,6 +93,19 @@ def merge(results):
         t["plain"] = max(r[key]["abs"] for r in results) / tot["R_ref_max" if key == "R" else "J_ref_max"]
         tot[key] = t
     return tot
+
+
+def icesheet_tetrahedra():
+    """The ice-sheet configuration extruded to tetrahedra (3 per prism)."""
+    from fo_inputs import config1_icesheet
+    m, U = config1_icesheet()
+    return m.with_fields(elem="tet"), U
+
+
+def marine_bench_sheet():
+    """The marine ice sheet the benchmark assembles (125k base points, 10 layers)."""
+    from fo_inputs import marine_sheet
+    return marine_sheet(seed=7, n_points=125_000, n_layers=10, a=600e3, b=350e3)
 
 
 def column_ranges(n_verts, n_chunks):

@@ -280,6 +280,21 @@ def test_assemble_rows_matches_full():
 # tetrahedral extrusion: the split of each prism into three tetrahedra
 # --------------------------------------------------------------------------------------
 
+def test_chunked_assembly_keeps_the_prism_pattern():
+    """Assembled in many chunks of cells, the tetrahedral Jacobian has the same pattern as in
+    one chunk and as the wedge mesh (node pairs of a prism that share no tetrahedron stay as
+    structural zeros) and the same values."""
+    m = _box_mesh(6, 5, 3, "tet", seed=4)
+    U = smooth_velocity(m, np.random.default_rng(2), 100.0, 0.05)
+    _, J1 = fo.assemble(m, U)
+    _, J7 = fo.assemble(m, U, chunk=7)
+    _, Jw = fo.assemble(m.with_fields(elem="wedge"), U, chunk=5)
+    for J in (J7, Jw):
+        assert np.array_equal(J.indptr, J1.indptr) and np.array_equal(J.indices, J1.indices)
+    assert (J1.data == 0).sum() > 0          # the structural zeros are there
+    assert np.abs(J7.data - J1.data).max() <= 1e-13 * np.abs(J1.data).max()
+
+
 def test_tet_split_is_conforming_and_fills_the_prisms():
     """Every triangular face of the tetrahedra is shared by exactly two of them or lies on
     the domain boundary (bed, surface, lateral sides), so neighbouring prisms split their
