@@ -169,3 +169,38 @@ def test_tetrahedral_ensemble_with_fronts_equals_single_mesh():
     w, _ = _box(3, 2, 2, "wedge", 70)
     with pytest.raises(_lib.FoError):
         Ensemble([Ms[0], gpu_mesh(w)])
+
+
+def test_full_size_64_member_ensemble():
+    """The benchmark's ensemble (64 seeded members of 10k-200k base triangles, 10 layers) in
+    one persistent launch: every member's residual and FP64 Jacobian bit for bit equal to its
+    own single-mesh assembly, and the smallest and the largest member, whole mesh, against the
+    oracle (every row, in host processes)."""
+    import functools
+    import multiprocessing as mp
+    import os
+
+    from paper_2204_04321_amd.api import Ensemble
+    from test_gpu_assembly import _full_mesh_parity
+    with mp.get_context("spawn").Pool(min(16, len(os.sched_getaffinity(0)))) as pool:
+        pairs = pool.map(ensemble_member, range(64))
+    meshes = [gpu_mesh(m) for m, _ in pairs]
+    cells = [M.n_cells for M in meshes]
+    print(f"\n[ensemble64] {sum(cells)} wedges, members {min(cells)}..{max(cells)}", flush=True)
+    E = Ensemble(meshes)
+    Us = [to_dev(U) for _, U in pairs]
+    Rs = [torch.full((M.n_dofs,), float("nan"), dtype=torch.float64, device="cuda") for M in meshes]
+    Js = [torch.full((M.nnz,), float("nan"), dtype=torch.float64, device="cuda") for M in meshes]
+    E.assemble(Us, Rs, Js)
+    torch.cuda.synchronize()
+    for i, (M, Ud) in enumerate(zip(meshes, Us)):
+        R1, J1 = M.jacobian(Ud)
+        torch.cuda.synchronize()
+        assert torch.equal(Rs[i], R1) and torch.equal(Js[i], J1), i
+        del R1, J1
+    print("[ensemble64] every member equals its single-mesh assembly bit for bit", flush=True)
+    small, large = int(np.argmin(cells)), int(np.argmax(cells))
+    del Rs, Js, E, meshes, Us
+    torch.cuda.empty_cache()
+    for i in (small, large):
+        _full_mesh_parity(functools.partial(ensemble_member, i), f"member{i}")
