@@ -245,8 +245,9 @@ fo_status fo_mdsc_aggregate_graph(int32_t n, const int32_t *ptr, const int32_t *
                                   int32_t *n_agg);
 
 /* Build the hierarchy's graphs, aggregates and transfer tables for a mesh (host work plus
- * device allocations; about 4(L+1)(2 nnz_plane + 3 V) doubles, nnz_plane the number of
- * base-vertex pairs that share a cell).  Synchronises `stream`. */
+ * device allocations: about (L+1)(2 nnz_plane + 15 V) doubles, nnz_plane the number of
+ * ordered base-vertex pairs that share a cell, self pairs included).  The mesh's device must
+ * be current.  Synchronises `stream`. */
 fo_status fo_mdsc_create(const fo_mesh *mesh, void *stream, fo_mdsc **out);
 void fo_mdsc_destroy(fo_mdsc *p);
 
@@ -269,7 +270,8 @@ fo_status fo_mdsc_setup(fo_mdsc *p, const void *J_dev, int32_t jac_dtype, void *
  * A fixed linear operator (right preconditioning); asynchronous on `stream`. */
 fo_status fo_mdsc_apply(const fo_mdsc *p, const double *r_dev, double *z_dev, void *stream);
 
-/* Copy numeric setup to the host: what = FO_MDSC_WEIGHTS (level ignored): the weights
+/* Copy the numeric setup of the last successful fo_mdsc_setup to the host (FO_EINVAL before
+ * one): what = FO_MDSC_WEIGHTS (level ignored): the weights
  * [V][L+1][2 c'][2 c] (count V (L+1) 4); FO_MDSC_PLANE: level `level`'s block values in its
  * graph order, block [2 c + d] (count 4 ptr[n]); FO_MDSC_BOUND: the Gershgorin bound of a
  * smoothed level (count 1).  Synchronises `stream`. */

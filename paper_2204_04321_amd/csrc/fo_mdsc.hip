@@ -771,6 +771,7 @@ extern "C" fo_status fo_mdsc_apply(const fo_mdsc *p, const double *r, double *z,
 extern "C" fo_status fo_mdsc_export(const fo_mdsc *p, int32_t what, int32_t level, double *host, size_t count,
                                     void *stream) {
   if (!p || !host) return fail(FO_EINVAL, "fo_mdsc_export: NULL argument");
+  if (!p->ready) return fail(FO_EINVAL, "fo_mdsc_export: no successful fo_mdsc_setup");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double *src = nullptr;
   size_t n = 0;

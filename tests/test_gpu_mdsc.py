@@ -273,6 +273,8 @@ def test_mdsc_argument_errors():
     U = to_dev(solve.sia_guess(m))
     with pytest.raises(FoError, match="no successful fo_mdsc_setup"):
         P.apply(torch.zeros_like(U))
+    with pytest.raises(FoError, match="no successful fo_mdsc_setup"):
+        P.export("weights")
     rep = M2.newton_solve(U.clone(), preconditioner="mdsc", mdsc=P)
     assert rep["status"] == -1 and "created on this mesh" in rep["message"]
     rep = M.newton_solve(U.clone(), preconditioner="mdsc", mdsc=P, linear_solver="pcg")
