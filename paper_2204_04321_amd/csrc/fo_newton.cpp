@@ -1,7 +1,8 @@
 // Damped Newton solve of F(U) = 0 (arXiv:2204.04321 Sec. 3.1, eq. linearsystem):
 // J(U_k) delta = -F(U_k), U_{k+1} = U_k + alpha_k delta.  Each linear system is solved
 // by restarted GMRES (Sec. 3.1) with right preconditioning by the vertical-column
-// block factorisation.  Readings where the paper is silent: alpha from backtracking
+// block factorisation, or by the two-level column semicoarsening preconditioner built on
+// it (Sec. 3.3, fo_mdsc).  Readings where the paper is silent: alpha from backtracking
 // 1, 1/2, 1/4, ... accepting ||F(U + alpha delta)|| <= (1 - 1e-4 alpha) ||F(U)||;
 // convergence when ||F(U)||_2 <= tol ||F(0)||_2 (F(0) is the gravity load and does
 // not depend on the initial guess).  The timers carry the paper's names (Sec. 5):
