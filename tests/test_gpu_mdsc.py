@@ -371,3 +371,36 @@ def test_icesheet_two_level_full_size():
     print(f"[icesheet newton] max |U_two_level - U_column| / max |U_column| = {diff:.1e}", flush=True)
     assert rm["newton_its"] == rc["newton_its"] and rm["lin_its"] < 0.75 * rc["lin_its"]
     assert diff <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["cap400_wedge", "cap400_tet", "slab_hex"])
+def test_setup_from_fp32_values_matches_oracle(name):
+    """The FP32-value setup path on the oracle's own Jacobian rounded to FP32 (written into the
+    library's layout through its CSR pattern, which equals the oracle's): weights, plane
+    operators and one application against the oracle's hierarchy of the same rounded values,
+    at the bars of the FP64 path."""
+    from paper_2204_04321_amd.api import Mdsc
+    m, U = _case(name)
+    M = gpu_mesh(m)
+    rowptr, colidx = M.pattern()
+    _, Jo = fo.assemble(m, U)
+    Jo = sp.csr_matrix(Jo)
+    assert np.array_equal(rowptr.cpu().numpy(), Jo.indptr) and np.array_equal(colidx.cpu().numpy(), Jo.indices)
+    J32 = Jo.data.astype(np.float32)
+    Jr = sp.csr_matrix((J32.astype(np.float64), Jo.indices, Jo.indptr), shape=Jo.shape)
+    P = Mdsc(M)
+    P.setup(torch.from_numpy(J32).cuda())
+    H = mdsc.Hierarchy(m, Jr)
+    W = P.export("weights").reshape(H.W.shape)
+    err_w = (np.abs(W - H.W) / np.abs(H.W).max(axis=(1, 2))[:, None, None, :]).max()
+    errs = []
+    for lvl in range(P.n_levels + 1):
+        ptr, idx, _ = P.graph(lvl)
+        A_o = _blocks_of(H.levels[lvl]["A"] if lvl < len(H.levels) else H.A_coarse, ptr, idx)
+        errs.append(np.abs(P.export("plane", lvl).reshape(-1, 4) - A_o).max() / np.abs(A_o).max())
+    r = np.random.default_rng(4).normal(size=m.n_dofs)
+    z = P.apply(to_dev(r)).cpu().numpy()
+    want = H.apply(r)
+    err_z = np.abs(z - want).max() / np.abs(want).max()
+    print(f"\n[mdsc fp32 values] {name}: weights {err_w:.1e}, plane {max(errs):.1e}, apply {err_z:.1e}")
+    assert err_w <= 1e-11 and max(errs) <= 1e-10 and err_z <= 1e-6
