@@ -117,8 +117,10 @@ fo_status fo_jacobian_pattern(const fo_mesh *mesh, int64_t *rowptr_dev, int32_t 
 fo_status fo_assemble_residual(const fo_mesh *mesh, const double *U_dev, double *R_dev,
                                void *stream);
 
-/* Jacobian J = dF/dU (eq. linearsystem) by forward-mode AD over the element
- * dofs, values written into Jvals_dev [nnz] of type `dtype` (FO_F64: double,
+/* Jacobian J = dF/dU (eq. linearsystem) in forward mode over the element dofs (Sec. 3.2):
+ * the tangent of each element residual row along every element dof, pushed through strain
+ * rate -> eps_e^2 -> mu -> residual by derivative rules written out in the kernel (not an
+ * operator-overloading AD type); values written into Jvals_dev [nnz] of type `dtype` (FO_F64: double,
  * FO_F32: float; with FO_F32 the per-cell derivatives are computed in FP32 over
  * an FP64 primal evaluation, summed over cells in FP64 and rounded once).  kind = FO_JAC_PICARD drops the viscosity-derivative
  * term.  If R_dev is not NULL the FP64 residual is written too, from the same
