@@ -282,6 +282,24 @@ def test_icesheet_tetrahedra_full_mesh_parity():
     _full_mesh_parity(oracle_pool.icesheet_tetrahedra, "icesheet_tet")
 
 
+def test_sia_guess_full_size():
+    """The shallow-ice guess of every column of the ice-sheet mesh and of the benchmarked
+    marine sheet (floating shelf included) against the oracle's (columns with beta = 0 and a
+    vanishing surface gradient left out, as in test_sia_parity)."""
+    import oracle_pool
+    for factory in (config1_icesheet, oracle_pool.marine_bench_sheet):
+        m, _ = factory()
+        M = gpu_mesh(m)
+        Ug = M.sia().cpu().numpy()
+        Uo = solve.sia_guess(m)
+        gx, gy = solve.vertex_surface_gradient(m)
+        keep = ~np.repeat((m.beta == 0) & (np.hypot(gx, gy) <= 1e-12), 2 * (m.n_layers + 1))
+        err = np.abs(Ug - Uo)[keep].max() / np.abs(Uo).max()
+        print(f"\n[sia full size] {m.name or factory.__name__}: {m.n_dofs} dofs, {err:.1e}", flush=True)
+        assert keep.sum() > 0.9 * keep.size and err <= 1e-12
+        M.close()
+
+
 def test_marine_sheet_full_mesh_parity():
     """The marine ice sheet of `bench.py --workload marine` (125k base points, 10 layers, a
     floating shelf with beta = 0 and ocean fronts on its seaward margin), whole mesh.  The
