@@ -159,21 +159,52 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
     if (fst != FO_OK) return fst;
   }
 
-  // neighbour lists: vertices sharing a base cell (each vertex neighbours itself)
-  std::vector<int64_t> keys;
-  keys.reserve(size_t(T) * nv * nv + V);
-  for (int64_t v = 0; v < V; ++v) keys.push_back(v * V + v);
-  for (int64_t t = 0; t < T; ++t)
-    for (int a = 0; a < nv; ++a)
-      for (int b = 0; b < nv; ++b) keys.push_back(int64_t(C[t * nv + a]) * V + C[t * nv + b]);
-  std::sort(keys.begin(), keys.end());
-  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-  std::vector<int32_t> nbr_ptr(V + 1, 0), nbr_idx(keys.size());
-  for (size_t i = 0; i < keys.size(); ++i) {
-    nbr_ptr[keys[i] / V + 1]++;
-    nbr_idx[i] = int32_t(keys[i] % V);
+  // vertex -> base cells (ordered by cell id): the owner-computes work items
+  std::vector<int32_t> vc_ptr(V + 1, 0), vc_idx(size_t(T) * nv), item_vtx(size_t(T) * nv);
+  std::vector<uint8_t> vc_pos(size_t(T) * nv);
+  for (int64_t i = 0; i < T * nv; ++i) vc_ptr[C[i] + 1]++;
+  for (int64_t v = 0; v < V; ++v) vc_ptr[v + 1] += vc_ptr[v];
+  {
+    std::vector<int32_t> fillp(vc_ptr.begin(), vc_ptr.end() - 1);
+    for (int64_t t = 0; t < T; ++t)
+      for (int a = 0; a < nv; ++a) {
+        const int32_t v = C[t * nv + a];
+        const int32_t p = fillp[v]++;
+        vc_idx[p] = int32_t(t);
+        vc_pos[p] = uint8_t(a);
+        item_vtx[p] = v;
+      }
   }
-  for (int64_t v = 0; v < V; ++v) nbr_ptr[v + 1] += nbr_ptr[v];
+  // neighbour lists: vertices sharing a base cell (each vertex neighbours itself), built
+  // column by column from the vertex's cells with a last-seen marker, then sorted (short
+  // lists: insertion sort)
+  std::vector<int32_t> nbr_ptr(V + 1, 0), nbr_idx;
+  nbr_idx.reserve(size_t(V) * 8);
+  {
+    std::vector<int32_t> mark(V, -1);
+    for (int64_t v = 0; v < V; ++v) {
+      const size_t b0 = nbr_idx.size();
+      nbr_idx.push_back(int32_t(v));
+      mark[v] = int32_t(v);
+      for (int32_t i = vc_ptr[v]; i < vc_ptr[v + 1]; ++i) {
+        const int64_t t = vc_idx[i];
+        for (int a = 0; a < nv; ++a) {
+          const int32_t w = C[t * nv + a];
+          if (mark[w] != int32_t(v)) {
+            mark[w] = int32_t(v);
+            nbr_idx.push_back(w);
+          }
+        }
+      }
+      for (size_t i = b0 + 1; i < nbr_idx.size(); ++i) {
+        const int32_t x = nbr_idx[i];
+        size_t j = i;
+        for (; j > b0 && nbr_idx[j - 1] > x; --j) nbr_idx[j] = nbr_idx[j - 1];
+        nbr_idx[j] = x;
+      }
+      nbr_ptr[v + 1] = int32_t(nbr_idx.size());
+    }
+  }
   std::vector<int32_t> deg(V), self_rank(V);
   std::vector<int64_t> colptr(V + 1, 0);
   for (int64_t v = 0; v < V; ++v) {
@@ -193,22 +224,6 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
         rank[(t * nv + a) * nv + b] = uint8_t(it - beg);
       }
     }
-  // vertex -> base cells (ordered by cell id): the owner-computes work items
-  std::vector<int32_t> vc_ptr(V + 1, 0), vc_idx(size_t(T) * nv), item_vtx(size_t(T) * nv);
-  std::vector<uint8_t> vc_pos(size_t(T) * nv);
-  for (int64_t i = 0; i < T * nv; ++i) vc_ptr[C[i] + 1]++;
-  for (int64_t v = 0; v < V; ++v) vc_ptr[v + 1] += vc_ptr[v];
-  {
-    std::vector<int32_t> fillp(vc_ptr.begin(), vc_ptr.end() - 1);
-    for (int64_t t = 0; t < T; ++t)
-      for (int a = 0; a < nv; ++a) {
-        const int32_t v = C[t * nv + a];
-        const int32_t p = fillp[v]++;
-        vc_idx[p] = int32_t(t);
-        vc_pos[p] = uint8_t(a);
-        item_vtx[p] = v;
-      }
-  }
   // wave tasks: runs of consecutive vertex columns with at most 64 items (one lane each)
   // whose level windows (12 D entries per vertex) fit the per-wave LDS budget
   // kMaxSlot: two level windows of at most 1200 FP64 entries (plus the residual windows) keep
