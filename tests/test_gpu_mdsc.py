@@ -404,3 +404,38 @@ def test_setup_from_fp32_values_matches_oracle(name):
     err_z = np.abs(z - want).max() / np.abs(want).max()
     print(f"\n[mdsc fp32 values] {name}: weights {err_w:.1e}, plane {max(errs):.1e}, apply {err_z:.1e}")
     assert err_w <= 1e-11 and max(errs) <= 1e-10 and err_z <= 1e-6
+
+
+def test_weights_fallback_columns_match_oracle():
+    """Columns whose block-tridiagonal solve gives a weight vector with non-positive mean
+    (here: the column blocks of every seventh column negated, so they are negative definite)
+    take the plain vertical average e_c on both sides; the rest of the setup is unaffected.
+    The Jacobian is the oracle's, written into the library's layout through its pattern."""
+    from paper_2204_04321_amd.api import Mdsc
+    m, U = _case("cap400_wedge")
+    M = gpu_mesh(m)
+    _, Jo = fo.assemble(m, U)
+    Jo = sp.csr_matrix(Jo).tocoo()
+    nb = 2 * (m.n_layers + 1)
+    col = Jo.row // nb
+    flip = ((col % 7) == 0) & (col == Jo.col // nb)
+    data = np.where(flip, -Jo.data, Jo.data)
+    Jm = sp.csr_matrix((data, (Jo.row, Jo.col)), shape=Jo.shape)
+    Jm.sort_indices()
+    rowptr, colidx = M.pattern()
+    assert np.array_equal(rowptr.cpu().numpy(), Jm.indptr) and np.array_equal(colidx.cpu().numpy(), Jm.indices)
+    P = Mdsc(M)
+    P.setup(torch.from_numpy(Jm.data.copy()).cuda())
+    H = mdsc.Hierarchy(m, Jm)
+    W = P.export("weights").reshape(H.W.shape)
+    e = np.zeros((m.n_layers + 1, 2, 2))
+    e[:, 0, 0] = e[:, 1, 1] = 1.0
+    fell = [v for v in range(m.n_verts) if np.array_equal(H.W[v], e)]
+    assert len(fell) >= m.n_verts // 7 - 1
+    assert all(np.array_equal(W[v], e) for v in fell)
+    err_w = (np.abs(W - H.W) / np.abs(H.W).max(axis=(1, 2))[:, None, None, :]).max()
+    ptr, idx, _ = P.graph(0)
+    A_o = _blocks_of(H.levels[0]["A"] if H.levels else H.A_coarse, ptr, idx)
+    err_a = np.abs(P.export("plane", 0).reshape(-1, 4) - A_o).max() / np.abs(A_o).max()
+    print(f"\n[mdsc fallback] {len(fell)} columns on e_c; weights {err_w:.1e}, plane {err_a:.1e}")
+    assert err_w <= 1e-11 and err_a <= 1e-10
