@@ -232,11 +232,14 @@ fo_status fo_newton_solve(const fo_mesh *mesh, double *U_dev, const fo_newton_op
  *                 unassigned roots an aggregate of itself and its neighbours, isolated
  *                 vertices are grouped 8 at a time; pass 2: every vertex left joins the
  *                 aggregate of its lowest-numbered neighbour assigned in pass 1), unsmoothed
- *                 transfers, Galerkin operators, Chebyshev degree 2 over [g/30, g] on
- *                 D^-1 A (D: 2x2 diagonal blocks, g: the Gershgorin bound max row sum of
- *                 |D^-1 A|) before and after the coarse correction, the coarsest level
- *                 solved by its inverse (Gauss-Jordan with partial pivoting);
- *   application:  y = V-cycle(P0^T r), z = P0 y + B^-1 (r - J P0 y).
+ *                 transfers, Galerkin operators, Chebyshev over [g/30, g] on D^-1 A (D: 2x2
+ *                 diagonal blocks, g: the Gershgorin bound max row sum of |D^-1 A|) before
+ *                 and after the coarse correction, degree 2 on the first plane level and 1
+ *                 below it, the coarsest level solved by its inverse (Gauss-Jordan with
+ *                 partial pivoting);
+ *   application:  y = V-cycle(P0^T r), z = P0 y + B^-1 (r - J P0 y), with J P0 and the weights
+ *                 of P0 and P0^T stored in FP32 (the plane operators are formed from the FP64
+ *                 values; any stored precision leaves M a fixed linear operator).
  * All device memory is allocated by fo_mdsc_create and owned by the object; the mesh must
  * outlive it.  Calls on one object must not overlap. */
 
