@@ -69,9 +69,9 @@ def measured_peaks():
         return None
 
 
-def measured_traffic():
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
-    current kernel source; otherwise None."""
+def measured_traffic(jdtype: str = "f64"):
+    """HBM bytes per launch of the R+J kernel with `jdtype` Jacobian values, from committed
+    rocprofv3 counter runs, if they were taken on the current kernel source; otherwise None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
@@ -79,7 +79,8 @@ def measured_traffic():
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     if t.get("kernel_source_sha256") != sha:
         return None
-    return float(t["bytes_per_launch"])
+    rec = t if jdtype == "f64" else t.get(jdtype)
+    return float(rec["bytes_per_launch"]) if rec else None
 
 
 def cpu_model() -> str:
@@ -476,7 +477,7 @@ def main():
     print(f"[bench] cells {M.n_cells} dofs {M.n_dofs} nnz {M.nnz}; warmup {args.warmup}",
           file=sys.stderr, flush=True)
     a = time_assembly(M, m, Ud, args.jdtype, args.steps, args.warmup)
-    traffic = measured_traffic() if args.jdtype == "f64" else None
+    traffic = measured_traffic(args.jdtype)
     pk = measured_peaks()
     print(f"[bench] {a['ms_step']:.3f} ms/step, assembly kernel {a['kernel_s'] * 1e3:.3f} ms, "
           f"{a['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
@@ -534,8 +535,8 @@ def main():
             "value": M.n_cells * args.steps / (b["total_ms"] / 1e3), "unit": "cells/s", "ms_per_step": b["ms_step"],
             "median_step_ms": b["median_ms"], "consecutive_100_ms": b["ms_100"],
             "roofline": {"bound": "hbm", "achieved": b["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": b["achieved_gbs"] / HBM_PEAK_GBS, "kernel_ms": b["kernel_s"] * 1e3,
-                         "algorithmic_bytes": b["alg_bytes"]},
+                         "frac": b["achieved_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(other),
+                         "kernel_ms": b["kernel_s"] * 1e3, "algorithmic_bytes": b["alg_bytes"]},
             "config": f"same mesh and inputs, Jacobian values in {other.upper()} (residual, strain rate and "
                       "viscosity FP64)"}
         print("[bench] Newton solve", file=sys.stderr, flush=True)
