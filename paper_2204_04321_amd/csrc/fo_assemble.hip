@@ -877,9 +877,14 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
         }
       }
     };
+    // The copy-out runs at raised wave priority: its LDS reads and streaming stores then issue
+    // ahead of the other wave's quadrature work instead of queuing behind it (FP64 R+J -2%,
+    // FP32 -2.5%; raising it for the window adds or the gather instead was slower).
+    __builtin_amdgcn_s_setprio(2);
     flush(k, cur);
     if (k == L - 1) flush(L, nxt);
     wave_sync();
+    __builtin_amdgcn_s_setprio(0);
 
   }
 }
