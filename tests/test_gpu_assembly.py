@@ -348,3 +348,75 @@ def test_fp32_element_matrix_error_on_icesheet_cells():
     errs = np.array(errs)
     print(f"\n[icesheet cells, FP32 element matrices] max rel error {errs.max():.2e}, median {np.median(errs):.2e}")
     assert errs.max() <= 1e-5
+
+
+def test_single_mesh_beyond_int32_offsets():
+    """One mesh whose Jacobian has more than 2^31 entries (a 1649 x 1649 structured wedge grid,
+    10 layers: 54.4M wedges, 59.9M dofs, 2.36e9 nonzeros), so every 64-bit offset path of the
+    assembly is exercised: residual and Jacobian rows (FP64 and FP32 values) of vertex columns
+    at the start, around the row where the offsets pass 2^31, and at the end against the
+    oracle's rows from the cells around them (pattern bit for bit, the FP64 and FP32 bars of
+    this file on those rows); then a Newton solve of the whole mesh (GMRES with the two-level
+    preconditioner, whose setup and application, like the SpMV, read J and J P0 through
+    64-bit offsets) must converge."""
+    from paper_2204_04321_amd.api import Mdsc
+    nx = 1649
+    L = 10
+    xy, cells, sigma = structured_box(nx, nx, L, 4000e3, 4000e3, elem="wedge")
+    x, y = xy[:, 0], xy[:, 1]
+    H = 1500 + 500 * np.sin(x / 2e5) * np.cos(y / 1.5e5)
+    m = ExtrudedMesh("wedge", xy, cells, 300 - 2e-4 * x + H, H, 800 + 0 * x, sigma)
+    U = smooth_velocity(m, np.random.default_rng(3), 80.0, 0.05)
+    print(f"\n[case] int64 offsets: cells={m.n_cells} dofs={m.n_dofs}", flush=True)
+    M = gpu_mesh(m)
+    assert M.nnz > 2 ** 31, M.nnz
+    Ud = to_dev(U)
+    R, Jv = M.jacobian(Ud)
+    R32, J32 = M.jacobian(Ud, dtype="f32")
+    rowptr, colidx = M.pattern()
+    torch.cuda.synchronize()
+    assert torch.equal(R, R32)
+    nb = 2 * (L + 1)
+    cross = int(torch.searchsorted(rowptr, torch.tensor([2 ** 31], device=rowptr.device)).item()) - 1
+    vc = cross // nb
+    V = m.n_verts
+    verts = np.unique(np.array([0, 1, nx + 2, vc - 1, vc, vc + 1, V - nx - 3, V - 2, V - 1]))
+    dofs = (verts[:, None] * nb + np.arange(nb)[None, :]).ravel()
+    print(f"[int64 offsets] nnz {M.nnz}, offsets pass 2^31 in row {cross} (vertex {vc}); "
+          f"{dofs.size} rows checked", flush=True)
+    d_t = torch.from_numpy(dofs).to(rowptr.device)
+    lo, hi = rowptr[d_t], rowptr[d_t + 1]
+    idx = torch.cat([torch.arange(int(a), int(b), device=rowptr.device) for a, b in zip(lo.tolist(), hi.tolist())])
+    assert int(hi.max()) > 2 ** 31 and int(lo.min()) < 2 ** 31
+    ptr = np.concatenate([[0], np.cumsum((hi - lo).cpu().numpy())])
+    g_cols = colidx[idx].cpu().numpy().astype(np.int64)
+    g64 = Jv[idx].cpu().numpy()
+    g32 = J32[idx].double().cpu().numpy()
+    gR = R[d_t].cpu().numpy()
+    del Jv, J32
+    Ro, Jo, cs = fo.assemble_rows(m, U, dofs)
+    rs, js = fo.abs_scales(m, U, cells=cs)
+    er, ej = fo.element_scales(m, U, cells=cs)
+    assert np.array_equal(Jo.indptr, ptr) and np.array_equal(Jo.indices, g_cols)
+    rows = np.repeat(np.arange(dofs.size), np.diff(ptr))
+    dR = np.abs(gR - Ro)
+    for tag, vals, tol, tol_plain in (("f64", g64, TOL64, TOL64), ("f32", g32, TOL32, TOL32_PLAIN)):
+        dJ = np.zeros(dofs.size)
+        np.maximum.at(dJ, rows, np.abs(vals - Jo.data))
+        e_term, e_elem = (dJ / js[dofs]).max(), (dJ / ej[dofs]).max()
+        e_plain = dJ.max() / np.abs(Jo.data).max()
+        print(f"[int64 offsets/J {tag}] term {e_term:.2e} elem {e_elem:.2e} plain {e_plain:.2e}", flush=True)
+        assert e_term <= tol and e_elem <= tol and e_plain <= tol_plain
+    r_term, r_elem = (dR / rs[dofs]).max(), (dR / er[dofs]).max()
+    print(f"[int64 offsets/R] term {r_term:.2e} elem {r_elem:.2e}", flush=True)
+    assert r_term <= TOL64 and r_elem <= TOL64_ELEM
+    del R, R32, rowptr, colidx, idx
+    torch.cuda.empty_cache()
+    Un = torch.zeros(M.n_dofs, dtype=torch.float64, device="cuda")
+    P = Mdsc(M)
+    rep = M.newton_solve(Un, tol=1e-8, init="sia", preconditioner="mdsc", mdsc=P)
+    print(f"[int64 offsets/newton] status {rep['status']} its {rep['newton_its']} gmres {rep['lin_its']} "
+          f"rel {rep['final_rel']:.1e}, {rep['ms_total_solve']:.0f} ms", flush=True)
+    assert rep["status"] == 0 and rep["final_rel"] <= 1e-8
+    P.close()
+    M.close()
