@@ -30,7 +30,7 @@ too, when the step's first value on the far side is dropped as an outlier.
 
 Defaults are the paper's: alpha = 0.005, k = 10, m = 3, w = 30.
 
-    python -m paper_2204_04321_amd.changepoint history.jsonl --key value [--lower-is-better]
+    python -m paper_2204_04321_amd.changepoint history.jsonl --key value [--alpha A] [-k K] [-m M] [-w W]
 """
 from __future__ import annotations
 
