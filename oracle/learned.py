@@ -2,7 +2,7 @@
 
 Not in the paper: a small per-column network predicts the initial velocity profile
 of each vertex column from column features; the Newton solve of Sec. 3.1 (eq.
-linearsystem) then starts from it.  The method it serves is judged only by the
+linearsystem) then starts from it.  The method it serves is assessed only by the
 Newton outcome (the network is not unique).  Definitions used by both this
 reference and the GPU kernels:
 
