@@ -115,6 +115,10 @@ CASES = {
     "tet_fan_64_cells": lambda: _fan(elem="tet"),
     "tet_glen_n1": lambda: (lambda mu: (mu[0].with_fields(n=1.0, A=2e-13), mu[1]))(_box(4, 3, 3, "tet", 19)),
     "tet_glen_n4": lambda: (lambda mu: (mu[0].with_fields(n=4.0, A=1e-20), mu[1]))(_box(4, 4, 3, "tet", 20)),
+    # degenerate velocity: U = 0 gives exactly zero strain rates, so the viscosity sits at its
+    # regularised cap and the Newton term of the Jacobian vanishes (a rigid translation is
+    # pinned on the oracle only: its strain rates are rounding noise that the cap amplifies)
+    "zero_velocity_wedge": lambda: (lambda mu: (mu[0], np.zeros_like(mu[1])))(_box(4, 3, 3, "wedge", 21)),
     # ocean back-pressure on marked lateral fronts; floating ice has beta = 0
     "ocean_front_slab_hex": lambda: _float_slab("hex"),
     "ocean_front_slab_wedge_steep": lambda: _float_slab("wedge", steep=True),
