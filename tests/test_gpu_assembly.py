@@ -49,6 +49,17 @@ def _box(nx, ny, L, elem, seed):
     return m, smooth_velocity(m, np.random.default_rng(seed), 80.0, 0.05)
 
 
+def _thin_margin(elem, seed):
+    """Thickness falling from 900 m to 1 m across the box (a land-terminating margin): the
+    thinnest columns have layers 0.1 m thick under cells 0.6 km wide."""
+    xy, cells, sigma = structured_box(8, 4, 10, 5e3, 2e3, elem=elem)
+    x = xy[:, 0]
+    H = 1.0 + 899.0 * (1.0 - x / 5e3) ** 2
+    m = ExtrudedMesh(elem, xy, cells, 200 + H, H, 500 + 0 * x, sigma)
+    m = perturbed(m, np.random.default_rng(seed), 0.2)
+    return m, smooth_velocity(m, np.random.default_rng(seed), 60.0, 0.05)
+
+
 def _graded_sigma(m):
     L = m.n_layers
     sg = 1 - (1 - np.linspace(0, 1, L + 1)) ** 1.5    # thinner layers at the bed
@@ -119,6 +130,8 @@ CASES = {
     # regularised cap and the Newton term of the Jacobian vanishes (a rigid translation is
     # pinned on the oracle only: its strain rates are rounding noise that the cap amplifies)
     "zero_velocity_wedge": lambda: (lambda mu: (mu[0], np.zeros_like(mu[1])))(_box(4, 3, 3, "wedge", 21)),
+    "thin_margin_wedge": lambda: _thin_margin("wedge", 23),
+    "thin_margin_tet": lambda: _thin_margin("tet", 24),
     # ocean back-pressure on marked lateral fronts; floating ice has beta = 0
     "ocean_front_slab_hex": lambda: _float_slab("hex"),
     "ocean_front_slab_wedge_steep": lambda: _float_slab("wedge", steep=True),
