@@ -39,6 +39,10 @@ def _case(name):
         m = _cap(50, L=3, seed=2)
     elif name == "single_layer":
         m = _cap(600, L=1, seed=3)
+    elif name == "cap500_wedge_L24":
+        # 24 layers: the weights and J P0 kernels run fewer columns (blocks) per workgroup to
+        # keep their LDS staging within 64 KB
+        m = _cap(500, L=24, seed=9)
     elif name == "graded_sigma":
         m = _cap(500, L=8, seed=4, sigma=np.linspace(0, 1, 9) ** 1.7)
     elif name in ("box_plane_64", "box_plane_65"):
@@ -71,7 +75,7 @@ def _slab_fields(xy, cells, sigma, seed):
 
 
 CASES = ["cap400_wedge", "cap3000_wedge_L10", "slab_hex", "cap400_tet", "tiny_exact_plane", "single_layer",
-         "graded_sigma", "box_plane_64", "box_plane_65", "islands_100"]
+         "graded_sigma", "box_plane_64", "box_plane_65", "islands_100", "cap500_wedge_L24"]
 
 
 def _oracle_levels(m):
