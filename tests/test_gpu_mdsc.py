@@ -207,14 +207,16 @@ def test_newton_with_mdsc_matches_oracle_solution(cap_solution, jdt):
     assert rep["lin_its"] < base["lin_its"], (rep["lin_its"], base["lin_its"])
 
 
-@pytest.mark.parametrize("which", ["tet_cap", "marine_fronts", "hex_slab"])
+@pytest.mark.parametrize("which", ["tet_cap", "marine_fronts", "hex_slab", "cap_24_layers"])
 def test_newton_with_mdsc_other_meshes(which):
     """Tetrahedral extrusion, a marine sheet with a floating shelf (beta = 0) and ocean fronts,
-    and the hexahedral slab: Newton with the two-level preconditioner against the oracle's
-    direct-solve Newton."""
+    the hexahedral slab and a cap with 24 layers: Newton with the two-level preconditioner
+    against the oracle's direct-solve Newton."""
     from paper_2204_04321_amd.api import Mdsc
     if which == "tet_cap":
         m = _cap(300, L=5, seed=21).with_fields(elem="tet")
+    elif which == "cap_24_layers":
+        m = _cap(150, L=24, seed=22)
     elif which == "marine_fronts":
         from fo_inputs import marine_sheet
         m, _ = marine_sheet(seed=5, n_points=400, n_layers=5)
