@@ -323,6 +323,13 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   const int v = act ? m.item_vtx[item] : vb;
   const int t = act ? m.vc_idx[item] : 0;
   const int al = act ? m.vc_pos[item] : 0;
+  // Prisms take their cell's corners in cyclic order starting at the item's own vertex, so
+  // that vertex is always corner 0 (a cyclic rotation keeps the triangle's orientation, and
+  // the triangle rules are invariant under it): its selections become constants and its
+  // Jacobian entries can be carried from layer to layer in registers (below).
+  constexpr bool ROT = NV == 3 && !TET;
+  const int rot = ROT ? al : 0;
+  const int al_own = ROT ? 0 : al;
   const int Dv = m.deg[v];
   const int soff = m.slot_off[v];
   // per-item integers fixed over the layers, packed: slot offset (12 bits, < 2048), degree
@@ -332,10 +339,11 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   // compiler hoists the derived addresses out of the layer loop and spills them, and every
   // reload costs a scratch round trip that serialises the layer's gather loads.
   const uint32_t imeta_base = uint32_t(soff) | (uint32_t(Dv) << 12) | (uint32_t(v - vb) << 20);
-  const uint32_t imeta_cell = imeta_base | (uint32_t(al) << 26);
+  const uint32_t imeta_cell = imeta_base | (uint32_t(al_own) << 26);
   const int slot_size = m.slot_off[ve - 1] + 12 * m.deg[ve - 1];
   // 8 bits per corner: its rank in v's neighbour list
-  const uint32_t irank = act ? m.item_rank[item] : 0u;
+  uint32_t irank = act ? m.item_rank[item] : 0u;
+  if constexpr (ROT) irank = ((irank >> (8 * rot)) | (irank << (8 * (3 - rot)))) & 0xFFFFFFu;
 
   // ---- per-item constants -----------------------------------------------------------------
   int vid[NV];
@@ -355,7 +363,10 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     }
   };
 #pragma unroll
-  for (int i = 0; i < NV; ++i) vid[i] = m.cells[int64_t(t) * NV + i];
+  for (int i = 0; i < NV; ++i) {
+    const int ci = ROT ? (i + rot >= 3 ? i + rot - 3 : i + rot) : i;
+    vid[i] = m.cells[int64_t(t) * NV + ci];
+  }
   load_geo(xl, yl, bed, Hh, su);
   // The layer loop walks the corners in lvid order with their neighbour ranks in lrank and
   // the item's corner al_loop: the cell's own order, or for tetrahedra the order of the
@@ -401,8 +412,8 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   }
   double lx_al = 0.0, ly_al = 0.0;
   if constexpr (NV == 3) {
-    lx_al = sel4(al, lxc[0], lxc[1], lxc[2], 0.0);
-    ly_al = sel4(al, lyc[0], lyc[1], lyc[2], 0.0);
+    lx_al = ROT ? lxc[0] : sel4(al, lxc[0], lxc[1], lxc[2], 0.0);
+    ly_al = ROT ? lyc[0] : sel4(al, lyc[0], lyc[1], lyc[2], 0.0);
   }
 
   // metadata of the task's vertex columns, one per lane (a task has at most 64 columns)
@@ -451,7 +462,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
       }
       const double nx = txy * tyz - txz * tyy, ny = txz * tyx - txx * tyz, nz = txx * tyy - txy * tyx;
       const double wb = Q.bw[r] * sqrt(nx * nx + ny * ny + nz * nz) * br;
-      const double la = sel4(al, Q.blam[r][0], Q.blam[r][1], Q.blam[r][2], Q.blam[r][NV - 1]);
+      const double la = ROT ? Q.blam[r][0] : sel4(al, Q.blam[r][0], Q.blam[r][1], Q.blam[r][2], Q.blam[r][NV - 1]);
       Rf0 += wb * ur * la;
       Rf1 += wb * vr * la;
 #pragma unroll
@@ -473,16 +484,20 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
 
   // FP32 tangents: the upper row's entries at the upper level of layer k are kept in
   // registers and added together with layer k + 1's lower-row entries at the same places,
-  // a quarter fewer LDS adds.  The FP64 kernel has no registers to spare for them (spills
-  // made it slower), so it adds both.  [c][d][corner]
+  // a quarter fewer LDS adds.  The FP64 kernel has no registers to spare for all twelve
+  // (spills made it slower); on prisms it carries the four of the item's own vertex (corner
+  // 0), the entries that every item of a vertex adds to the same window places.
   constexpr bool CARRY = JAC && sizeof(JT) == 4;
-  AT carry[2][2][NV];
+  constexpr bool CARRY0 = JAC && ROT && !CARRY;
+  AT carry[2][2][NV], carry0[2][2];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int d = 0; d < 2; ++d)
+    for (int d = 0; d < 2; ++d) {
+      carry0[c][d] = AT(0);
 #pragma unroll
       for (int j = 0; j < NV; ++j) carry[c][d][j] = AT(0);
+    }
 
   for (int k = 0; k < L; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
@@ -582,7 +597,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
           dvm = fma(li, dv[i], dvm);
         }
         const double iz = rcp64(zze);
-        const double lam_a = sel4(al, Q.lam[tp][0], Q.lam[tp][1], Q.lam[tp][2], 0.0);
+        const double lam_a = ROT ? Q.lam[tp][0] : sel4(al, Q.lam[tp][0], Q.lam[tp][1], Q.lam[tp][2], 0.0);
         const double uz = iz * dum, vz = iz * dvm;
 #pragma unroll 1
         for (int zi = 0; zi < 2; ++zi) {
@@ -815,9 +830,12 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
                 if (a == 0) {
                   AT lo = Jx[0][c][d][j][lev];
                   if (CARRY && lev == 0) lo += carry[c][d][j];
+                  if (CARRY0 && lev == 0 && j == 0) lo += carry0[c][d];
                   lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, double(lo));
                 } else if (CARRY && lev == 1 && k + 1 < L) {
                   carry[c][d][j] = Jx[1][c][d][j][1];
+                } else if (CARRY0 && lev == 1 && j == 0 && k + 1 < L) {
+                  carry0[c][d] = Jx[1][c][d][0][1];
                 } else {
                   lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, double(Jx[1][c][d][j][lev]));
                 }
