@@ -93,7 +93,7 @@ typedef struct fo_mesh fo_mesh;
  * solution-independent data, Sec. 4.1) and upload them.  FO_EDEGENERATE also
  * if a base vertex lies in no base cell.  On FO_EDEGENERATE nothing is
  * allocated.  FO_EINVAL also if a base vertex lies in more than 64
- * base cells or has more than 100 neighbouring base vertices (one wave assembles
+ * base cells or has more than 90 neighbouring base vertices, itself included (one wave assembles
  * a vertex column's rows in its share of the compute unit's LDS), or if a front edge is
  * not a boundary edge of the base mesh, appears twice, or a vertex lies on more than four
  * front edges.  The front loads are integrated once here (memoised with the rest).

@@ -484,20 +484,20 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
 
   // FP32 tangents: the upper row's entries at the upper level of layer k are kept in
   // registers and added together with layer k + 1's lower-row entries at the same places,
-  // a quarter fewer LDS adds.  The FP64 kernel has no registers to spare for all twelve
-  // (spills made it slower); on prisms it carries the four of the item's own vertex (corner
-  // 0), the entries that every item of a vertex adds to the same window places.
+  // a quarter fewer LDS adds.  The FP64 kernel has no registers to spare for them (spills
+  // made it slower); on prisms it carries the four of the item's own vertex (corner 0),
+  // which every item of a vertex adds to the same window places, in a per-lane LDS slot
+  // after the residual windows (registers spilled them to scratch every layer).
   constexpr bool CARRY = JAC && sizeof(JT) == 4;
   constexpr bool CARRY0 = JAC && ROT && !CARRY;
-  AT carry[2][2][NV], carry0[2][2];
+  AT carry[2][2][NV];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      carry0[c][d] = AT(0);
+    for (int d = 0; d < 2; ++d)
 #pragma unroll
       for (int j = 0; j < NV; ++j) carry[c][d][j] = AT(0);
-    }
+  double *carry0 = Rw + 4 * size_t(max_tv) + 4 * lane;   // [c][d] of this lane
 
   for (int k = 0; k < L; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
@@ -830,12 +830,12 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
                 if (a == 0) {
                   AT lo = Jx[0][c][d][j][lev];
                   if (CARRY && lev == 0) lo += carry[c][d][j];
-                  if (CARRY0 && lev == 0 && j == 0) lo += carry0[c][d];
+                  if (CARRY0 && lev == 0 && j == 0 && k > 0) lo += carry0[2 * c + d];
                   lds_add(Wk + c * 2 * nlk * Dv + rk[j] * 2 * nlk + 2 * (lev + offk) + d, double(lo));
                 } else if (CARRY && lev == 1 && k + 1 < L) {
                   carry[c][d][j] = Jx[1][c][d][j][1];
                 } else if (CARRY0 && lev == 1 && j == 0 && k + 1 < L) {
-                  carry0[c][d] = Jx[1][c][d][0][1];
+                  carry0[2 * c + d] = double(Jx[1][c][d][0][1]);
                 } else {
                   lds_add(Wk1 + c * 2 * nl1 * Dv + rk[j] * 2 * nl1 + 2 * lev + d, double(Jx[1][c][d][j][lev]));
                 }
@@ -970,8 +970,11 @@ fo_status ensure_tables(int device) {
 }
 
 // LDS of one task: two level windows (Jacobian) and two residual windows
+// Dynamic LDS of one task: the two Jacobian level windows, the two residual windows and,
+// with a Jacobian, the per-lane carry slots (WAVE x 4 FP64) that follow them.
 size_t window_bytes(bool jac, int max_slot, int max_tv) {
-  return (jac ? 2 * size_t(max_slot) * sizeof(double) : 0) + 2 * 2 * size_t(max_tv) * sizeof(double);
+  return (jac ? 2 * size_t(max_slot) * sizeof(double) + size_t(WAVE) * 4 * sizeof(double) : 0) +
+         2 * 2 * size_t(max_tv) * sizeof(double);
 }
 
 template <int NV, bool JAC, class JT, bool N3, bool TET>

@@ -226,9 +226,10 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
     }
   // wave tasks: runs of consecutive vertex columns with at most 64 items (one lane each)
   // whose level windows (12 D entries per vertex) fit the per-wave LDS budget
-  // kMaxSlot: two level windows of at most 1200 FP64 entries (plus the residual windows) keep
-  // a wave's LDS under 20 KB, so that eight waves share a compute unit
-  constexpr int kMaxItems = 64, kMaxSlot = 1200;
+  // kMaxSlot: two level windows of at most 1080 FP64 entries, the residual windows and the
+  // per-lane carry slots (2 KB) keep a wave's LDS under 20 KB, so that eight waves share a
+  // compute unit
+  constexpr int kMaxItems = 64, kMaxSlot = 1080;
   std::vector<int4> tasks;
   std::vector<int32_t> slot_off(V);
   int32_t max_slot = 0, max_tv = 0;
@@ -242,7 +243,7 @@ extern "C" fo_status fo_mesh_create(const fo_mesh_desc *d, void *stream, fo_mesh
       if (ni > kMaxItems)
         return fail(FO_EINVAL, "fo_mesh_create: vertex " + std::to_string(v) + " lies in more than 64 base cells");
       if (sz > kMaxSlot)
-        return fail(FO_EINVAL, "fo_mesh_create: vertex " + std::to_string(v) + " has more than 100 neighbouring vertices");
+        return fail(FO_EINVAL, "fo_mesh_create: vertex " + std::to_string(v) + " has more than 90 neighbouring vertices");
       if (v > vb && (items + ni > kMaxItems || slot + sz > kMaxSlot)) {
         tasks.push_back(make_int4(0, vb, v, vc_ptr[vb]));
         max_slot = std::max(max_slot, slot);
