@@ -790,6 +790,10 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
   
     }
 
+    // The window adds run at wave priority 1 and the copy-out at 2 (below): the other wave's
+    // quadrature work then fills the LDS queue's gaps (about -1% each; priority for the adds
+    // above the copy-out's, or for the quadrature loop, was slower).
+    __builtin_amdgcn_s_setprio(1);
     // ---- add v's rows into the level windows ------------------------------------------------
     // (tetrahedra: every lane adds, lanes without an item add zeros to in-range entries; the
     // register allocator placed spills of live values inside the branch on `act` there)
@@ -897,7 +901,7 @@ __device__ __forceinline__ void owner_task(const MeshView &m, const int4 task, c
     };
     // The copy-out runs at raised wave priority: its LDS reads and streaming stores then issue
     // ahead of the other wave's quadrature work instead of queuing behind it (FP64 R+J -2%,
-    // FP32 -2.5%; raising it for the window adds or the gather instead was slower).
+    // FP32 -2.5%; raising the gather instead was slower).
     __builtin_amdgcn_s_setprio(2);
     flush(k, cur);
     if (k == L - 1) flush(L, nxt);
